@@ -1,0 +1,183 @@
+/* lidarscout.h - C-ABI of the MI355X (gfx950) per-tile heightmap library.
+ *
+ * The library implements the data-parallel hot path of LidarScout (Erler,
+ * Herzberger, Wimmer, Schuetz, HPG 2025): sparse "chunk points" are binned
+ * into fixed patches ("tiles" here) with a padding ring, interpolated into
+ * nearest-neighbour and Delaunay-linear height + colour maps (Section 3.3,
+ * Algorithm 1), normalised (Section 3.4), refined by a small convolutional
+ * network (Section 3.4), and full-resolution points are later splatted into
+ * the heightmap textures with packed 64-bit keys (Sections 3.5 and 3.6).
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers (memory of the current HIP device) unless
+ *    the comment says (host).  The caller owns every buffer; the library
+ *    never allocates device memory inside these calls.  Scratch memory is a
+ *    caller-provided workspace of at least ls_workspace_bytes() bytes.
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *    void*; NULL = the default stream).  No call synchronises the host, so
+ *    every call can be captured into a HIP graph.
+ *  - Return value: LS_OK (0) or a negative ls_status for argument errors,
+ *    detected on the host before anything is enqueued.  Errors that depend
+ *    on data are reported per tile in tile_status (bit flags ls_tile_flag)
+ *    and never abort a call.
+ *  - Coordinates are LAS raw integers: metres = raw * scale (+ offset for z).
+ *  - Layouts are row-major; images are NHWC: [tile][row][col][channel], row
+ *    index along +y, column index along +x.
+ */
+#ifndef LIDARSCOUT_H
+#define LIDARSCOUT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Region and tiling, passed by (host) pointer.
+ * Tile (tx, ty) covers [origin + t*tile_size, origin + (t+1)*tile_size) on
+ * each axis.  Its output grid has res x res texels of cell = tile_size/res
+ * raw units (640 m / 64 = 10 m in the paper, Section 3.1).  Its network
+ * input is the padded grid of R = res + 2*pad texels per side (96 with the
+ * paper's 16-texel ring, Section 3.3), covering the window
+ * [c - H, c + H) with c the tile centre and H = tile_size/2 + pad*cell.
+ * Requirements: tile_size % res == 0, cell even, R % 4 == 0, pad >= 0,
+ * 1 <= res, H < 2^16.5 raw units after scaling checks (H <= 65535). */
+typedef struct ls_grid {
+  int64_t origin_x, origin_y;
+  int32_t tile_size;
+  int32_t res, pad;
+  int32_t tiles_x, tiles_y;
+  double scale_xy, scale_z, offset_z;
+} ls_grid;
+
+typedef enum ls_status {
+  LS_OK = 0,
+  LS_EINVAL = -1,     /* null pointer or inconsistent size */
+  LS_ERANGE = -2,     /* grid parameters out of the supported range */
+  LS_EHIP = -3,       /* HIP runtime error (see ls_last_error) */
+  LS_ENOTIMPL = -4,   /* option not implemented */
+  LS_EWORKSPACE = -5, /* workspace smaller than ls_workspace_bytes() */
+  LS_ECAP = -6        /* a caller-sized output cannot hold the result */
+} ls_status;
+
+/* per-tile status flags written by ls_recon_tiles */
+typedef enum ls_tile_flag {
+  LS_TILE_EMPTY = 1,      /* no point in the window: all outputs 0, cz = 0 */
+  LS_TILE_NN_ONLY = 2,    /* < 3 distinct points or all collinear: linear = NN */
+  LS_TILE_CAP = 4,        /* bin_cap too small; bin_off[n_tiles] holds the need */
+  LS_TILE_DEGENERATE = 8, /* triangulation safeguard hit (never expected) */
+  LS_TILE_BADID = 16      /* tile id outside the region or listed twice */
+} ls_tile_flag;
+
+typedef enum ls_precision { LS_FP32 = 0, LS_BF16 = 1 } ls_precision;
+
+typedef enum ls_op { LS_OP_RECON = 0, LS_OP_REFINE = 1, LS_OP_BACKWARD = 2, LS_OP_SPLAT = 3 } ls_op;
+
+/* Number of network parameters (119,844 for the 3-level U-Net).
+ * Flat FP32 layout, layers in order enc1a 8->16, enc1b 16->16, enc2a 16->32,
+ * enc2b 32->32, bot_a 32->64, bot_b 64->64, dec2a 96->32, dec2b 32->32,
+ * dec1a 48->16, dec1b 16->16, head 24->4; per layer W[Cout][3][3][Cin]
+ * followed by b[Cout]. */
+int ls_num_params(void);
+
+/* Bytes of caller workspace needed by `op` for n_tiles tiles and n_points
+ * input points (recon: sparse points; splat: unused, returns 0).  Depends
+ * only on the sizes, never on the data. */
+size_t ls_workspace_bytes(int op, const ls_grid* g, int32_t n_tiles, int64_t n_points, int precision);
+
+/* Bytes of the activation buffer ls_refine_tiles can save for
+ * ls_refine_backward (FP32 or BF16 activations, per `precision`). */
+size_t ls_act_bytes(const ls_grid* g, int32_t n_tiles, int precision);
+
+/* Tile binning + Algorithm 1 + normalisation (Sections 3.3-3.4).
+ *  x, y, z [n] int32 raw; rgb [n][3] uint16 (16-bit LAS colour).
+ *  tile_list [n_tiles]: linear tile ids ty*tiles_x + tx, distinct, in the
+ *    order tiles are to be processed (e.g. by distance to the viewer,
+ *    which the paper uses to prioritise construction).  Output slot k
+ *    belongs to tile_list[k].
+ *  x_out [n_tiles][R][R][8] FP32: channel 0 (h_lin - cz)/r, 1 (h_nn - cz)/r,
+ *    2-4 linear RGB/65535, 5-7 nearest RGB/65535, with r = H*scale_xy
+ *    metres and h in metres.
+ *  cz_out [n_tiles] FP64: the linear height (metres) at texel (R/2, R/2).
+ *  bin_off [n_tiles+1], bin_idx [bin_cap] (both nullable together): if
+ *    given, receive the CSR of point indices in each tile's window in
+ *    ascending index order; if bin_cap is too small every tile gets
+ *    LS_TILE_CAP and bin_off[n_tiles] the required size.
+ *  tile_status [n_tiles]: ls_tile_flag bits.
+ *  ws: workspace of ls_workspace_bytes(LS_OP_RECON, g, n_tiles, n, 0).
+ * Points outside every listed window are ignored.  Nearest-neighbour ties
+ * go to the smallest (d^2, y, x); duplicate positions keep the largest
+ * (z, R, G, B).  Linear values cover exactly the closed convex hull. */
+int ls_recon_tiles(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                   int64_t n, const int32_t* tile_list, int32_t n_tiles, float* x_out, double* cz_out,
+                   int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* Refinement network forward (Section 3.4) on a batch of tiles.
+ *  w [num_params] FP32; w_bf16 [num_params] BF16 bit patterns (required
+ *    for LS_BF16, from ls_pack_weights_bf16; ignored for LS_FP32).
+ *  x [n_tiles][R][R][8] FP32 (from ls_recon_tiles); cz [n_tiles] FP64.
+ *  y_out [n_tiles][res][res][4] FP32 normalised (h, r, g, b); nullable.
+ *  tex_out [n_tiles][res][res][4] FP32 texture: h = cz + r*y_h metres,
+ *    rgb = clamp(y_rgb, 0, 1); nullable (cz may then be NULL).
+ *  act_save: nullable; if given (ls_act_bytes bytes) the activations the
+ *    backward needs are kept there.
+ *  LS_FP32: FP32 operands and accumulation.  LS_BF16: BF16 operands on
+ *  the matrix cores, FP32 accumulation, FP32 bias/residual/denormalise.
+ *  ws: ls_workspace_bytes(LS_OP_REFINE, g, n_tiles, 0, precision). */
+int ls_refine_tiles(const float* w, const uint16_t* w_bf16, int precision, const float* x, const double* cz,
+                    int32_t n_tiles, const ls_grid* g, float* y_out, float* tex_out, void* act_save, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* Refinement network backward: given dL/dy [n_tiles][res][res][4] for the
+ * normalised output, writes grad_w [num_params] (overwritten, summed over
+ * the batch) and, if non-null, grad_x [n_tiles][R][R][8].  act_save: the
+ * buffer filled by ls_refine_tiles with the same inputs and precision, or
+ * NULL to recompute the forward inside (activation recomputation).
+ *  ws: ls_workspace_bytes(LS_OP_BACKWARD, g, n_tiles, 0, precision). */
+int ls_refine_backward(const float* w, const uint16_t* w_bf16, int precision, const float* x,
+                       const void* act_save, const float* grad_y, int32_t n_tiles, const ls_grid* g, float* grad_w,
+                       float* grad_x, void* ws, size_t ws_bytes, void* stream);
+
+/* Full-resolution splat (Sections 3.5-3.6): every point with texel
+ * gx = floor((x - origin_x)/cell), gy likewise, inside the region and in a
+ * tile whose tile_slot[ty*tiles_x + tx] >= 0, raises
+ *   keys[slot][gy % res][gx % res] = max(old, key),
+ *   key = ((uint32)z ^ 0x80000000) << 32 | R>>8 << 24 | G>>8 << 16 | B>>8 << 8 | 0xFF,
+ * i.e. the texel keeps its highest point (ties: larger packed colour).
+ * keys [n_slots][res][res] accumulate across calls (caller zeroes them
+ * once).  *n_dropped (device, uint64) is incremented by the number of
+ * points outside the region or in unmapped tiles.  tex_inout (nullable,
+ * [n_slots][res][res][4] FP32): afterwards every texel whose key is
+ * non-zero is overwritten with h = (float)(z*scale_z + offset_z) (double
+ * multiply then add, correctly rounded) and byte/255 colours; other texels
+ * keep their value.  Any point order is accepted; Morton-ordered input
+ * (50,000-point chunks of Section 3.1) is the fast case. */
+int ls_splat_points(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                    int64_t n, const int32_t* tile_slot, int32_t n_slots, uint64_t* keys, float* tex_inout,
+                    uint64_t* n_dropped, void* stream);
+
+/* Resolve only (the second half of ls_splat_points). */
+int ls_resolve_keys(const ls_grid* g, const uint64_t* keys, int32_t n_slots, float* tex_inout, void* stream);
+
+/* FP32 -> BF16 (round to nearest even) weight copy for LS_BF16. */
+int ls_pack_weights_bf16(const float* w, uint16_t* w_bf16, void* stream);
+
+/* Conv tiling selection used by the autotuner: config index per
+ * (layer 0..10, precision, pass 0=forward 1=dgrad 2=wgrad); -1 = default.
+ * ls_conv_num_configs reports how many configs a (layer, precision, pass)
+ * accepts.  Host-side state, applies to later calls in this process. */
+int ls_conv_num_configs(int layer, int precision, int pass);
+int ls_set_conv_config(int layer, int precision, int pass, int config);
+int ls_get_conv_config(int layer, int precision, int pass);
+
+const char* ls_status_string(int status);
+/* Text of the last LS_EHIP error on this thread (host string). */
+const char* ls_last_error(void);
+const char* ls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIDARSCOUT_H */

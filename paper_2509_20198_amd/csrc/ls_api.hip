@@ -1,0 +1,177 @@
+// C-ABI entry points of liblidarscout (declared in include/lidarscout.h):
+// argument validation on the host, then the enqueue functions of the other
+// translation units.
+#include <stdio.h>
+#include <string.h>
+
+#include "ls_common.hpp"
+#include "ls_unet_bf16.hpp"
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+__global__ void k_zero_f32(float* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+// per (layer, precision, pass) selected conv tiling; -1 = default
+int g_conv_cfg[LS_NLAYER][2][3] = {};
+bool g_conv_cfg_init = false;
+
+void cfg_init() {
+  if (g_conv_cfg_init) return;
+  for (int l = 0; l < LS_NLAYER; ++l)
+    for (int p = 0; p < 2; ++p)
+      for (int q = 0; q < 3; ++q) g_conv_cfg[l][p][q] = -1;
+  g_conv_cfg_init = true;
+}
+
+}  // namespace
+
+void ls_set_last_error(hipError_t e, const char* what, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s (%d) at %s, line %d", hipGetErrorString(e), (int)e, what, line);
+}
+
+int ls_zero_f32(float* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return LS_OK;
+  const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_zero_f32, dim3(blocks), dim3(256), 0, st, p, n);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_conv_num_configs_impl(int layer, int precision, int pass) {
+  if (layer < 0 || layer >= LS_NLAYER || precision < 0 || precision > 1 || pass < 0 || pass > 2) return 0;
+  return 1;
+}
+int ls_conv_config_get(int layer, int precision, int pass) {
+  cfg_init();
+  if (layer < 0 || layer >= LS_NLAYER || precision < 0 || precision > 1 || pass < 0 || pass > 2) return -1;
+  return g_conv_cfg[layer][precision][pass];
+}
+int ls_conv_config_set(int layer, int precision, int pass, int config) {
+  cfg_init();
+  if (layer < 0 || layer >= LS_NLAYER || precision < 0 || precision > 1 || pass < 0 || pass > 2) return LS_ERANGE;
+  if (config < -1 || config >= ls_conv_num_configs_impl(layer, precision, pass)) return LS_ERANGE;
+  g_conv_cfg[layer][precision][pass] = config;
+  return LS_OK;
+}
+
+extern "C" {
+
+int ls_num_params(void) { return LS_NUM_PARAMS; }
+
+const char* ls_version(void) { return "lidarscout-mi355x 0.1 (gfx950)"; }
+
+const char* ls_last_error(void) { return g_last_error; }
+
+const char* ls_status_string(int status) {
+  switch (status) {
+    case LS_OK: return "ok";
+    case LS_EINVAL: return "invalid argument (null pointer or size)";
+    case LS_ERANGE: return "grid or option out of the supported range";
+    case LS_EHIP: return "HIP runtime error (see ls_last_error)";
+    case LS_ENOTIMPL: return "not implemented";
+    case LS_EWORKSPACE: return "workspace smaller than ls_workspace_bytes()";
+    case LS_ECAP: return "output capacity too small";
+    default: return "unknown status";
+  }
+}
+
+size_t ls_workspace_bytes(int op, const ls_grid* g, int32_t n_tiles, int64_t n_points, int precision) {
+  LsGridInfo gi;
+  if (ls_grid_info(g, &gi) != LS_OK || n_tiles < 0 || n_points < 0) return 0;
+  switch (op) {
+    case LS_OP_RECON: return ls_recon_ws_bytes(gi, n_tiles, n_points);
+    case LS_OP_REFINE: return ls_refine_ws_bytes(gi, n_tiles, precision, 0);
+    case LS_OP_BACKWARD: return ls_refine_ws_bytes(gi, n_tiles, precision, 1);
+    default: return 0;
+  }
+}
+
+size_t ls_act_bytes(const ls_grid* g, int32_t n_tiles, int precision) {
+  LsGridInfo gi;
+  if (ls_grid_info(g, &gi) != LS_OK || n_tiles < 0) return 0;
+  return ls_refine_act_bytes(gi, n_tiles, precision);
+}
+
+int ls_recon_tiles(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                   int64_t n, const int32_t* tile_list, int32_t n_tiles, float* x_out, double* cz_out,
+                   int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
+                   size_t ws_bytes, void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (n < 0 || n_tiles < 0 || n > 0x7fffffffLL) return LS_EINVAL;
+  if (n > 0 && (!x || !y || !z || !rgb)) return LS_EINVAL;
+  if (n_tiles > 0 && (!tile_list || !x_out || !cz_out || !tile_status)) return LS_EINVAL;
+  if ((bin_off == nullptr) != (bin_idx == nullptr)) return LS_EINVAL;
+  if (bin_idx && bin_cap < 0) return LS_EINVAL;
+  if ((int64_t)gi.tx * gi.ty > 0x7fffffffLL) return LS_ERANGE;
+  return ls_recon_impl(gi, x, y, z, rgb, n, tile_list, n_tiles, x_out, cz_out, bin_off, bin_idx, bin_cap,
+                       tile_status, ws, ws_bytes, ls_stream(stream));
+}
+
+int ls_refine_tiles(const float* w, const uint16_t* w_bf16, int precision, const float* x, const double* cz,
+                    int32_t n_tiles, const ls_grid* g, float* y_out, float* tex_out, void* act_save, void* ws,
+                    size_t ws_bytes, void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (precision != LS_FP32 && precision != LS_BF16) return LS_ERANGE;
+  if (n_tiles < 0) return LS_EINVAL;
+  if (n_tiles > 0 && (!w || !x)) return LS_EINVAL;
+  if (precision == LS_BF16 && !w_bf16) return LS_EINVAL;
+  if (tex_out && !cz) return LS_EINVAL;
+  return ls_refine_forward_impl(w, w_bf16, precision, x, cz, n_tiles, gi, y_out, tex_out, act_save, ws, ws_bytes,
+                                ls_stream(stream));
+}
+
+int ls_refine_backward(const float* w, const uint16_t* w_bf16, int precision, const float* x,
+                       const void* act_save, const float* grad_y, int32_t n_tiles, const ls_grid* g, float* grad_w,
+                       float* grad_x, void* ws, size_t ws_bytes, void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (precision != LS_FP32 && precision != LS_BF16) return LS_ERANGE;
+  if (n_tiles < 0 || !grad_w) return LS_EINVAL;
+  if (n_tiles > 0 && (!w || !x || !grad_y)) return LS_EINVAL;
+  if (precision == LS_BF16 && !w_bf16) return LS_EINVAL;
+  return ls_refine_backward_impl(w, w_bf16, precision, x, act_save, grad_y, n_tiles, gi, grad_w, grad_x, ws,
+                                 ws_bytes, ls_stream(stream));
+}
+
+int ls_splat_points(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                    int64_t n, const int32_t* tile_slot, int32_t n_slots, uint64_t* keys, float* tex_inout,
+                    uint64_t* n_dropped, void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (n < 0 || n_slots < 0) return LS_EINVAL;
+  if (n > 0 && (!x || !y || !z || !rgb || !tile_slot || !keys || !n_dropped)) return LS_EINVAL;
+  if (tex_inout && !keys) return LS_EINVAL;
+  return ls_splat_impl(gi, x, y, z, rgb, n, tile_slot, n_slots, keys, tex_inout, n_dropped, ls_stream(stream));
+}
+
+int ls_resolve_keys(const ls_grid* g, const uint64_t* keys, int32_t n_slots, float* tex_inout, void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (n_slots < 0 || (n_slots > 0 && (!keys || !tex_inout))) return LS_EINVAL;
+  return ls_resolve_impl(gi, keys, n_slots, tex_inout, ls_stream(stream));
+}
+
+int ls_pack_weights_bf16(const float* w, uint16_t* w_bf16, void* stream) {
+  if (!w || !w_bf16) return LS_EINVAL;
+  return ls_pack_bf16(w, w_bf16, LS_NUM_PARAMS, ls_stream(stream));
+}
+
+int ls_conv_num_configs(int layer, int precision, int pass) { return ls_conv_num_configs_impl(layer, precision, pass); }
+int ls_set_conv_config(int layer, int precision, int pass, int config) {
+  return ls_conv_config_set(layer, precision, pass, config);
+}
+int ls_get_conv_config(int layer, int precision, int pass) { return ls_conv_config_get(layer, precision, pass); }
+
+}  // extern "C"

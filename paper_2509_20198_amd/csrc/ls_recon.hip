@@ -1,0 +1,899 @@
+// Tile binning and per-tile interpolated heightmaps (LidarScout Section 3.3,
+// Algorithm 1; normalisation of Section 3.4) for gfx950.
+//
+// Pipeline of ls_recon_tiles, all on one stream, no host round trip:
+//   1. k_init / k_tile_pos: map linear tile id -> output slot.
+//   2. k_bin_count, k_bin_scan, k_bin_scatter: CSR of the points in every
+//      listed tile's padded window [c - H, c + H)^2 (a point sits in 1, 2 or
+//      4 windows with the paper's 16-texel ring).
+//   3. k_bin_sort (only when the caller asks for the CSR): ascending order.
+//   4. k_recon: persistent, one workgroup per tile popped from a queue in
+//      tile_list order.  Phases, separated by barriers:
+//        a. gather the tile's points to tile-local coordinates and bucket
+//           them into a G x G grid over the window (LDS counting sort);
+//        b. sort each bucket by (v, u) and drop duplicate positions,
+//           keeping the largest (z, R, G, B) -> canonical points;
+//        c. nearest point of every texel centre (exact int64 distances,
+//           ties by (d^2, v, u)) by ring search over the buckets;
+//        d. Delaunay triangulation: every point computes its own star by
+//           gift-wrapping (first point hit by a circle growing from a
+//           Delaunay edge), with exact orientation and in-circle tests and a
+//           symbolic perturbation of the lifted heights (lower canonical
+//           index = larger perturbation) that makes the triangulation unique
+//           when points are cocircular.  A triangle is rasterised by its
+//           lowest-index vertex into a per-texel face map (top-left rule),
+//           hull edges by one endpoint, so every texel of the closed convex
+//           hull gets a containing triangle;
+//        e. c_z from the centre texel, then per texel: barycentric height and
+//           colour inside the hull, nearest point outside it (the paper's
+//           corner padding points taken at infinity), normalised and written
+//           as one NHWC row of 8 FP32 channels.
+#include <algorithm>
+
+#include "ls_common.hpp"
+
+namespace {
+
+constexpr int RB = 256;                  // threads per recon workgroup
+constexpr int MAXG = 90;                 // max buckets per side
+constexpr int MAXB = MAXG * MAXG;        // max buckets
+constexpr int STAR_MAX_STEPS = 1024;     // safeguard on one point's star walk
+constexpr uint64_t FACE_NONE = ~0ull;
+constexpr int SORT_LDS = 16384;          // bin segments up to this size sort in LDS
+
+struct BinParams {
+  int64_t ox, oy;
+  int32_t S, H, tiles_x, tiles_y, K;
+  int32_t n_tiles;
+  int64_t n;
+  const int32_t* x;
+  const int32_t* y;
+  const int32_t* tile_pos;
+  int32_t* counts;
+  int32_t* fill;
+  int32_t* bin_off;
+  int32_t* bin_idx;
+  int64_t cap;
+  int32_t* flags;  // [0]: cap overflow
+};
+
+// Visit every listed tile whose padded window contains point i.
+template <class F>
+__device__ __forceinline__ void for_each_window(const BinParams& p, int64_t i, F&& f) {
+  const int64_t px = p.x[i], py = p.y[i];
+  const int64_t tx0 = ls_floordiv(px - p.ox, p.S), ty0 = ls_floordiv(py - p.oy, p.S);
+  for (int64_t ty = ty0 - p.K; ty <= ty0 + p.K; ++ty) {
+    if (ty < 0 || ty >= p.tiles_y) continue;
+    const int64_t cy = p.oy + ty * p.S + p.S / 2;
+    if (py < cy - p.H || py >= cy + p.H) continue;
+    for (int64_t tx = tx0 - p.K; tx <= tx0 + p.K; ++tx) {
+      if (tx < 0 || tx >= p.tiles_x) continue;
+      const int64_t cx = p.ox + tx * p.S + p.S / 2;
+      if (px < cx - p.H || px >= cx + p.H) continue;
+      const int32_t s = p.tile_pos[ty * p.tiles_x + tx];
+      if (s >= 0) f(s);
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+__global__ void k_tile_pos(const int32_t* __restrict__ tile_list, int32_t n_tiles, int64_t n_all,
+                           int32_t* __restrict__ tile_pos, int32_t* __restrict__ status) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_tiles) return;
+  const int32_t t = tile_list[k];
+  if (t < 0 || t >= n_all) {
+    status[k] = LS_TILE_BADID;
+    return;
+  }
+  // lowest slot wins for a tile listed twice; the others are flagged
+  atomicMin(&tile_pos[t], k);
+}
+
+__global__ void k_tile_dup(const int32_t* __restrict__ tile_list, int32_t n_tiles, int64_t n_all,
+                           const int32_t* __restrict__ tile_pos, int32_t* __restrict__ status) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_tiles) return;
+  const int32_t t = tile_list[k];
+  if (t >= 0 && t < n_all && tile_pos[t] != k) status[k] = LS_TILE_BADID;
+}
+
+__global__ void k_tile_pos_fix(int32_t* __restrict__ tile_pos, int64_t n_all) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_all; i += (int64_t)gridDim.x * blockDim.x)
+    if (tile_pos[i] == 0x7fffffff) tile_pos[i] = -1;
+}
+
+__global__ void k_bin_count(BinParams p) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * blockDim.x)
+    for_each_window(p, i, [&](int32_t s) { atomicAdd(&p.counts[s], 1); });
+}
+
+// Single-workgroup exclusive scan of counts -> bin_off (n_tiles + 1 entries).
+__global__ void __launch_bounds__(1024) k_bin_scan(BinParams p) {
+  __shared__ int64_t s_part[1024];
+  __shared__ int64_t s_carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < p.n_tiles; base += 1024) {
+    const int64_t i = base + tid;
+    const int64_t v = i < p.n_tiles ? p.counts[i] : 0;
+    s_part[tid] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int64_t t = tid >= o ? s_part[tid - o] : 0;
+      __syncthreads();
+      s_part[tid] += t;
+      __syncthreads();
+    }
+    const int64_t excl = s_carry + s_part[tid] - v;
+    if (i < p.n_tiles) p.bin_off[i] = (int32_t)(excl < 0x7fffffff ? excl : 0x7fffffff);
+    __syncthreads();
+    if (tid == 1023) s_carry += s_part[1023];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int64_t total = s_carry;
+    p.bin_off[p.n_tiles] = (int32_t)(total < 0x7fffffff ? total : 0x7fffffff);
+    p.flags[0] = total > p.cap ? 1 : 0;
+  }
+}
+
+__global__ void k_bin_scatter(BinParams p) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * blockDim.x)
+    for_each_window(p, i, [&](int32_t s) {
+      const int32_t r = atomicAdd(&p.fill[s], 1);
+      const int64_t pos = (int64_t)p.bin_off[s] + r;
+      if (pos < p.cap) p.bin_idx[pos] = (int32_t)i;
+    });
+}
+
+// In-place ascending bitonic sort of one bin segment; segments longer than
+// SORT_LDS use `scratch` (2 entries per bin entry, so the power-of-two
+// padding always fits).
+__global__ void __launch_bounds__(RB) k_bin_sort(const int32_t* __restrict__ bin_off, int32_t n_tiles,
+                                                 int32_t* __restrict__ bin_idx, int32_t* __restrict__ scratch,
+                                                 const int32_t* __restrict__ flags) {
+  __shared__ int32_t s_buf[SORT_LDS];
+  if (flags[0]) return;
+  for (int k = blockIdx.x; k < n_tiles; k += gridDim.x) {
+    const int32_t off = bin_off[k];
+    const int32_t cnt = bin_off[k + 1] - off;
+    if (cnt <= 1) continue;
+    int n2 = 1;
+    while (n2 < cnt) n2 <<= 1;
+    int32_t* buf = n2 <= SORT_LDS ? s_buf : scratch + 2 * (int64_t)off;
+    for (int i = threadIdx.x; i < n2; i += RB) buf[i] = i < cnt ? bin_idx[off + i] : 0x7fffffff;
+    __syncthreads();
+    for (int kk = 2; kk <= n2; kk <<= 1)
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < n2; i += RB) {
+          const int l = i ^ j;
+          if (l > i) {
+            const int32_t a = buf[i], b = buf[l];
+            const bool asc = (i & kk) == 0;
+            if ((a > b) == asc) {
+              buf[i] = b;
+              buf[l] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (int i = threadIdx.x; i < cnt; i += RB) bin_idx[off + i] = buf[i];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// per-tile reconstruction
+// ---------------------------------------------------------------------------
+struct ReconParams {
+  int64_t ox, oy;
+  int32_t S, tiles_x, C, R, H;
+  double scale_z, offset_z, inv_r;
+  int32_t n_tiles;
+  const int32_t* x;
+  const int32_t* y;
+  const int32_t* z;
+  const uint16_t* rgb;
+  const int32_t* tile_list;
+  const int32_t* bin_off;
+  const int32_t* bin_idx;
+  const int32_t* flags;
+  // per bin entry scratch: staging (reused for the canonical points) and sorted
+  int32_t* su;
+  int32_t* sv;
+  int32_t* sz;
+  uint64_t* srgb;  // R | G << 16 | B << 32
+  int32_t* sslot;
+  int32_t* tu;
+  int32_t* tv;
+  int32_t* tz;
+  uint64_t* trgb;
+  // per workgroup scratch
+  uint64_t* facemap;  // [gridDim][R*R]
+  int32_t* nnidx;     // [gridDim][R*R]
+  int32_t* queue;
+  float* x_out;
+  double* cz_out;
+  int32_t* status;
+};
+
+struct Tile {
+  const int32_t* u;
+  const int32_t* v;
+  const int32_t* boff;  // LDS, G*G + 1
+  int G, H, W2;
+  double bw;  // bucket width in raw units
+};
+
+__device__ __forceinline__ int bucket_1d(int w, int G, int W2) { return (int)(((int64_t)w * G) / W2); }
+
+__device__ __forceinline__ double orient_d(double ax, double ay, double bx, double by, double px, double py) {
+  // exact: |differences| < 2^17, products < 2^34, result < 2^35
+  return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
+}
+
+__device__ __forceinline__ int sgn_d(double v) { return (v > 0.0) - (v < 0.0); }
+
+// Sign of the in-circle determinant of d against CCW (a, b, c): > 0 when d
+// is strictly inside.  Floating-point filter first, exact int128 otherwise,
+// then the symbolic perturbation for exactly cocircular points.
+__device__ int incircle_sos(const Tile& T, int a, int b, int c, int d) {
+  const int64_t ux = T.u[d], uy = T.v[d];
+  const int64_t adx = T.u[a] - ux, ady = T.v[a] - uy;
+  const int64_t bdx = T.u[b] - ux, bdy = T.v[b] - uy;
+  const int64_t cdx = T.u[c] - ux, cdy = T.v[c] - uy;
+  const double fadx = (double)adx, fady = (double)ady, fbdx = (double)bdx, fbdy = (double)bdy;
+  const double fcdx = (double)cdx, fcdy = (double)cdy;
+  const double al = fadx * fadx + fady * fady;
+  const double bl = fbdx * fbdx + fbdy * fbdy;
+  const double cl = fcdx * fcdx + fcdy * fcdy;
+  const double bc = fbdx * fcdy - fcdx * fbdy;
+  const double ca = fcdx * fady - fadx * fcdy;
+  const double ab = fadx * fbdy - fbdx * fady;
+  const double t1 = al * bc, t2 = bl * ca, t3 = cl * ab;
+  const double det = t1 + t2 + t3;
+  const double perm = fabs(t1) + fabs(t2) + fabs(t3);
+  if (fabs(det) > 8.8817841970012523e-16 * perm) return sgn_d(det);  // 8 * 2^-53
+  const __int128 e = (__int128)(adx * adx + ady * ady) * (__int128)(bdx * cdy - cdx * bdy) +
+                     (__int128)(bdx * bdx + bdy * bdy) * (__int128)(cdx * ady - adx * cdy) +
+                     (__int128)(cdx * cdx + cdy * cdy) * (__int128)(adx * bdy - bdx * ady);
+  if (e > 0) return 1;
+  if (e < 0) return -1;
+  int w = a;
+  if (b < w) w = b;
+  if (c < w) w = c;
+  if (d < w) w = d;
+  if (w == d) return -1;
+  auto o = [&](int p, int q, int r) {
+    return sgn_d(orient_d(T.u[p], T.v[p], T.u[q], T.v[q], T.u[r], T.v[r]));
+  };
+  if (w == a) return o(b, c, d);
+  if (w == b) return o(c, a, d);
+  return o(a, b, d);
+}
+
+// Visit the buckets at Chebyshev ring r around (bx0, by0); returns false if
+// the ring lies completely outside the grid.
+template <class F>
+__device__ __forceinline__ void ring_visit(const Tile& T, int bx0, int by0, int r, F&& f) {
+  const int G = T.G;
+  const int ylo = by0 - r, yhi = by0 + r, xlo = bx0 - r, xhi = bx0 + r;
+  for (int by = ylo < 0 ? 0 : ylo; by <= (yhi < G ? yhi : G - 1); ++by) {
+    const bool full = (by == ylo || by == yhi);
+    const int step = full ? 1 : (xhi - xlo);
+    for (int bx = xlo; bx <= xhi; bx += (step > 0 ? step : 1)) {
+      if (bx < 0 || bx >= G) continue;
+      const int b = by * G + bx;
+      for (int p = T.boff[b]; p < T.boff[b + 1]; ++p) f(p);
+    }
+  }
+}
+
+__device__ __forceinline__ bool ring_covers_grid(const Tile& T, int bx0, int by0, int r) {
+  return bx0 - r <= 0 && by0 - r <= 0 && bx0 + r >= T.G - 1 && by0 + r >= T.G - 1;
+}
+
+// Nearest canonical point to (qx, qy), ties by smallest (d^2, v, u); skips
+// point `skip`.  Returns -1 if no point.
+__device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
+  const int bx0 = bucket_1d(qx + T.H, T.G, T.W2), by0 = bucket_1d(qy + T.H, T.G, T.W2);
+  int best = -1;
+  int64_t bd = 0;
+  int bu = 0, bv = 0;
+  for (int r = 0;; ++r) {
+    ring_visit(T, bx0, by0, r, [&](int p) {
+      if (p == skip) return;
+      const int pu = T.u[p], pv = T.v[p];
+      const int64_t dx = pu - qx, dy = pv - qy;
+      const int64_t d = dx * dx + dy * dy;
+      if (best < 0 || d < bd || (d == bd && (pv < bv || (pv == bv && pu < bu)))) {
+        best = p;
+        bd = d;
+        bu = pu;
+        bv = pv;
+      }
+    });
+    if (best >= 0) {
+      const double L = r * T.bw - 2.0;  // lower bound on the distance of unvisited points
+      if (L > 0.0 && (double)bd < L * L) break;
+    }
+    if (ring_covers_grid(T, bx0, by0, r)) break;
+  }
+  return best;
+}
+
+// The third vertex of the Delaunay triangle on the left of edge a->b: the
+// first point met by a circle through a and b whose centre moves left.
+// Returns -1 if no point lies strictly left of a->b (a->b is a hull edge).
+__device__ int third_left(const Tile& T, int a, int b) {
+  const int ax = T.u[a], ay = T.v[a], bx = T.u[b], by = T.v[b];
+  const int mx = (ax + bx) >> 1, my = (ay + by) >> 1;
+  const int bx0 = bucket_1d(mx + T.H, T.G, T.W2), by0 = bucket_1d(my + T.H, T.G, T.W2);
+  int best = -1;
+  double stop = 0.0;
+  const double fbx = bx - ax, fby = by - ay;
+  const double bl = fbx * fbx + fby * fby;
+  for (int r = 0;; ++r) {
+    ring_visit(T, bx0, by0, r, [&](int p) {
+      if (p == a || p == b) return;
+      const double px = T.u[p], py = T.v[p];
+      if (orient_d(ax, ay, bx, by, px, py) <= 0.0) return;
+      if (best < 0 || incircle_sos(T, a, b, best, p) > 0) {
+        best = p;
+        // circumcircle of (a, b, p) relative to a, and its reach from the midpoint
+        const double cx = px - ax, cy = py - ay;
+        const double cl = cx * cx + cy * cy;
+        const double D = 2.0 * (fbx * cy - fby * cx);
+        const double ox = (cy * bl - fby * cl) / D, oy = (fbx * cl - cx * bl) / D;
+        const double rho = sqrt(ox * ox + oy * oy);
+        const double dmx = ox - (mx - ax), dmy = oy - (my - ay);
+        stop = (sqrt(dmx * dmx + dmy * dmy) + rho) * (1.0 + 1e-9) + 2.0;
+      }
+    });
+    if (best >= 0 && r * T.bw - 2.0 > stop) break;
+    if (ring_covers_grid(T, bx0, by0, r)) break;
+  }
+  return best;
+}
+
+__device__ __forceinline__ uint64_t face_key(int a, int b, int c) {
+  // rotate so the lowest index comes first (keeps CCW order)
+  if (b < a && b < c) {
+    const int t = a;
+    a = b;
+    b = c;
+    c = t;
+  } else if (c < a && c < b) {
+    const int t = c;
+    c = b;
+    b = a;
+    a = t;
+  }
+  return ((uint64_t)a << 42) | ((uint64_t)b << 21) | (uint64_t)c;
+}
+
+// Top-left ownership of an edge P->Q for points exactly on it: equivalent to
+// testing the point nudged by an infinitesimal (-1, -delta).
+__device__ __forceinline__ bool edge_owned(int px, int py, int qx, int qy) {
+  const int dy = qy - py, dx = qx - px;
+  return dy > 0 || (dy == 0 && dx < 0);
+}
+
+__device__ __forceinline__ int floor_div_i(int a, int b) {
+  int q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+// texel index range covering [lo, hi] in tile-local raw coordinates
+__device__ __forceinline__ void texel_range(int lo, int hi, int H, int C, int R, int& j0, int& j1) {
+  const int q0 = -H + C / 2;
+  j0 = -floor_div_i(q0 - lo, C);  // ceil((lo - q0) / C)
+  j1 = floor_div_i(hi - q0, C);
+  if (j0 < 0) j0 = 0;
+  if (j1 > R - 1) j1 = R - 1;
+}
+
+__device__ void raster_triangle(const Tile& T, int a, int b, int c, int C, int R, uint64_t* __restrict__ fm) {
+  const int ax = T.u[a], ay = T.v[a], bx = T.u[b], by = T.v[b], cx = T.u[c], cy = T.v[c];
+  int i0, i1, j0, j1;
+  texel_range(min(ax, min(bx, cx)), max(ax, max(bx, cx)), T.H, C, R, j0, j1);
+  texel_range(min(ay, min(by, cy)), max(ay, max(by, cy)), T.H, C, R, i0, i1);
+  const bool oa = edge_owned(bx, by, cx, cy), ob = edge_owned(cx, cy, ax, ay), oc = edge_owned(ax, ay, bx, by);
+  const uint64_t key = face_key(a, b, c);
+  const int q0 = -T.H + C / 2;
+  for (int i = i0; i <= i1; ++i) {
+    const double qy = q0 + i * C;
+    for (int j = j0; j <= j1; ++j) {
+      const double qx = q0 + j * C;
+      const double e0 = orient_d(bx, by, cx, cy, qx, qy);
+      if (e0 < 0.0 || (e0 == 0.0 && !oa)) continue;
+      const double e1 = orient_d(cx, cy, ax, ay, qx, qy);
+      if (e1 < 0.0 || (e1 == 0.0 && !ob)) continue;
+      const double e2 = orient_d(ax, ay, bx, by, qx, qy);
+      if (e2 < 0.0 || (e2 == 0.0 && !oc)) continue;
+      fm[i * R + j] = key;
+    }
+  }
+}
+
+// Texels lying exactly on hull edge a->b get the triangle next to it.
+__device__ void raster_hull_edge(const Tile& T, int a, int b, uint64_t key, int C, int R, uint64_t* __restrict__ fm) {
+  const int ax = T.u[a], ay = T.v[a], bx = T.u[b], by = T.v[b];
+  int i0, i1, j0, j1;
+  texel_range(min(ax, bx), max(ax, bx), T.H, C, R, j0, j1);
+  texel_range(min(ay, by), max(ay, by), T.H, C, R, i0, i1);
+  const int q0 = -T.H + C / 2;
+  for (int i = i0; i <= i1; ++i)
+    for (int j = j0; j <= j1; ++j)
+      if (orient_d(ax, ay, bx, by, q0 + j * C, q0 + i * C) == 0.0) fm[i * R + j] = key;
+}
+
+__device__ int block_scan_excl(int* s, int n, int* s_tmp) {
+  const int tid = threadIdx.x;
+  const int per = (n + RB - 1) / RB;
+  const int beg = min(n, tid * per), end = min(n, beg + per);
+  int sum = 0;
+  for (int i = beg; i < end; ++i) sum += s[i];
+  const int lane = tid & 63, wid = tid >> 6;
+  int v = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  if (lane == 63) s_tmp[wid] = v;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int w = 0; w < RB / 64; ++w) {
+      const int t = s_tmp[w];
+      s_tmp[w] = run;
+      run += t;
+    }
+    s_tmp[RB / 64] = run;
+  }
+  __syncthreads();
+  int excl = v - sum + s_tmp[wid];
+  for (int i = beg; i < end; ++i) {
+    const int t = s[i];
+    s[i] = excl;
+    excl += t;
+  }
+  const int total = s_tmp[RB / 64];
+  __syncthreads();
+  return total;
+}
+
+__device__ __forceinline__ bool pt_less(int u0, int v0, int z0, uint64_t c0, int u1, int v1, int z1, uint64_t c1) {
+  // order by (v, u) ascending, then (z, R, G, B) descending
+  if (v0 != v1) return v0 < v1;
+  if (u0 != u1) return u0 < u1;
+  if (z0 != z1) return z0 > z1;
+  const uint64_t k0 = ((c0 & 0xFFFF) << 32) | (((c0 >> 16) & 0xFFFF) << 16) | ((c0 >> 32) & 0xFFFF);
+  const uint64_t k1 = ((c1 & 0xFFFF) << 32) | (((c1 >> 16) & 0xFFFF) << 16) | ((c1 >> 32) & 0xFFFF);
+  return k0 > k1;
+}
+
+__device__ __forceinline__ void write_zero_tile(const ReconParams& P, int k) {
+  const int64_t n8 = (int64_t)P.R * P.R * 2;
+  float4* o = reinterpret_cast<float4*>(P.x_out + (int64_t)k * P.R * P.R * 8);
+  for (int64_t i = threadIdx.x; i < n8; i += RB) o[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
+  __shared__ int s_b[MAXB + 1];  // bucket counts -> offsets (raw)
+  __shared__ int s_k[MAXB + 1];  // kept counts -> canonical bucket offsets
+  __shared__ int s_tmp[RB / 64 + 1];
+  __shared__ int s_tile;
+  __shared__ int s_flags;
+  __shared__ double s_cz;
+  const int tid = threadIdx.x;
+  const int R = P.R, C = P.C, H = P.H, W2 = 2 * P.H;
+  const int RR = R * R;
+  uint64_t* __restrict__ fm = P.facemap + (int64_t)blockIdx.x * RR;
+  int32_t* __restrict__ nn = P.nnidx + (int64_t)blockIdx.x * RR;
+  const bool cap_overflow = P.flags[0] != 0;
+  for (;;) {
+    if (tid == 0) s_tile = atomicAdd(P.queue, 1);
+    __syncthreads();
+    const int k = s_tile;
+    __syncthreads();
+    if (k >= P.n_tiles) break;
+    const int32_t t = P.tile_list[k];
+    int flags = 0;
+    if (cap_overflow) flags |= LS_TILE_CAP;
+    const int prev = P.status[k];
+    flags |= prev & LS_TILE_BADID;
+    const int32_t off = P.bin_off[k];
+    const int32_t cnt = (flags & (LS_TILE_CAP | LS_TILE_BADID)) ? 0 : P.bin_off[k + 1] - off;
+    if (cnt == 0) {
+      write_zero_tile(P, k);
+      if (tid == 0) {
+        P.cz_out[k] = 0.0;
+        P.status[k] = flags | LS_TILE_EMPTY;
+      }
+      continue;
+    }
+    const int64_t cx = P.ox + (int64_t)(t % P.tiles_x) * P.S + P.S / 2;
+    const int64_t cy = P.oy + (int64_t)(t / P.tiles_x) * P.S + P.S / 2;
+    int G = 1;
+    {
+      const int want = (int)sqrtf((float)cnt * 0.5f);
+      G = want < 1 ? 1 : (want > MAXG ? MAXG : want);
+    }
+    const int NB = G * G;
+    // ---- a. gather + bucket histogram
+    for (int b = tid; b <= NB; b += RB) s_b[b] = 0;
+    if (tid == 0) s_flags = 0;
+    __syncthreads();
+    for (int e = tid; e < cnt; e += RB) {
+      const int32_t gi = P.bin_idx[off + e];
+      const int u = (int)((int64_t)P.x[gi] - cx), v = (int)((int64_t)P.y[gi] - cy);
+      P.su[off + e] = u;
+      P.sv[off + e] = v;
+      P.sz[off + e] = P.z[gi];
+      const uint16_t* c3 = P.rgb + 3 * (int64_t)gi;
+      P.srgb[off + e] = (uint64_t)c3[0] | ((uint64_t)c3[1] << 16) | ((uint64_t)c3[2] << 32);
+      const int b = bucket_1d(v + H, G, W2) * G + bucket_1d(u + H, G, W2);
+      P.sslot[off + e] = atomicAdd(&s_b[b], 1);
+    }
+    __syncthreads();
+    block_scan_excl(s_b, NB + 1, s_tmp);
+    for (int e = tid; e < cnt; e += RB) {
+      const int u = P.su[off + e], v = P.sv[off + e];
+      const int b = bucket_1d(v + H, G, W2) * G + bucket_1d(u + H, G, W2);
+      const int pos = off + s_b[b] + P.sslot[off + e];
+      P.tu[pos] = u;
+      P.tv[pos] = v;
+      P.tz[pos] = P.sz[off + e];
+      P.trgb[pos] = P.srgb[off + e];
+    }
+    __syncthreads();
+    // ---- b. per-bucket sort + dedupe
+    if (tid == 0) s_k[NB] = 0;
+    for (int b = tid; b < NB; b += RB) {
+      const int lo = off + s_b[b], hi = off + s_b[b + 1];
+      for (int i = lo + 1; i < hi; ++i) {
+        const int u = P.tu[i], v = P.tv[i], zz = P.tz[i];
+        const uint64_t c = P.trgb[i];
+        int j = i - 1;
+        while (j >= lo && pt_less(u, v, zz, c, P.tu[j], P.tv[j], P.tz[j], P.trgb[j])) {
+          P.tu[j + 1] = P.tu[j];
+          P.tv[j + 1] = P.tv[j];
+          P.tz[j + 1] = P.tz[j];
+          P.trgb[j + 1] = P.trgb[j];
+          --j;
+        }
+        P.tu[j + 1] = u;
+        P.tv[j + 1] = v;
+        P.tz[j + 1] = zz;
+        P.trgb[j + 1] = c;
+      }
+      int kept = 0;
+      for (int i = lo; i < hi; ++i)
+        if (i == lo || P.tu[i] != P.tu[i - 1] || P.tv[i] != P.tv[i - 1]) ++kept;
+      s_k[b] = kept;
+    }
+    __syncthreads();
+    const int m = block_scan_excl(s_k, NB + 1, s_tmp);
+    for (int b = tid; b < NB; b += RB) {
+      const int lo = off + s_b[b], hi = off + s_b[b + 1];
+      int w = off + s_k[b];
+      for (int i = lo; i < hi; ++i)
+        if (i == lo || P.tu[i] != P.tu[i - 1] || P.tv[i] != P.tv[i - 1]) {
+          P.su[w] = P.tu[i];
+          P.sv[w] = P.tv[i];
+          P.sz[w] = P.tz[i];
+          P.srgb[w] = P.trgb[i];
+          ++w;
+        }
+    }
+    __syncthreads();
+    Tile T;
+    T.u = P.su + off;
+    T.v = P.sv + off;
+    T.boff = s_k;
+    T.G = G;
+    T.H = H;
+    T.W2 = W2;
+    T.bw = (double)W2 / G;
+    const int32_t* Tz = P.sz + off;
+    const uint64_t* Tc = P.srgb + off;
+    // ---- c. nearest point per texel; face map reset
+    const int q0 = -H + C / 2;
+    for (int tt = tid; tt < RR; tt += RB) {
+      const int i = tt / R, j = tt - i * R;
+      nn[tt] = ring_nearest(T, q0 + j * C, q0 + i * C, -1);
+      fm[tt] = FACE_NONE;
+    }
+    // collinearity check
+    bool noncol = false;
+    if (m >= 3)
+      for (int p = tid; p < m; p += RB)
+        if (orient_d(T.u[0], T.v[0], T.u[1], T.v[1], T.u[p], T.v[p]) != 0.0) noncol = true;
+    // face keys pack three point indices in 21 bits each
+    const bool has_dt = (__syncthreads_or(noncol) != 0) && m < (1 << 21);
+    if (m >= (1 << 21) && tid == 0) atomicOr(&s_flags, LS_TILE_DEGENERATE);
+    // ---- d. Delaunay stars, rasterised into the face map
+    if (has_dt) {
+      for (int a = tid; a < m; a += RB) {
+        const int b0 = ring_nearest(T, T.u[a], T.v[a], a);
+        int b = b0;
+        bool closed = false;
+        int steps = 0;
+        int prev_b = -1;      // second vertex of the last CCW triangle
+        uint64_t hull_key = FACE_NONE;
+        int hull_b = -1;
+        while (steps++ < STAR_MAX_STEPS) {
+          const int c = third_left(T, a, b);
+          if (c < 0) {
+            hull_b = b;
+            if (prev_b >= 0) hull_key = face_key(a, prev_b, b);
+            break;
+          }
+          if (a < b && a < c) raster_triangle(T, a, b, c, C, R, fm);
+          prev_b = b;
+          b = c;
+          if (b == b0) {
+            closed = true;
+            break;
+          }
+        }
+        if (!closed && steps <= STAR_MAX_STEPS) {
+          b = b0;
+          bool first = true;
+          while (steps++ < STAR_MAX_STEPS) {
+            const int c = third_left(T, b, a);  // triangle (b, a, c)
+            if (c < 0) break;
+            if (first && hull_key == FACE_NONE) hull_key = face_key(b, a, c);
+            first = false;
+            if (a < b && a < c) raster_triangle(T, b, a, c, C, R, fm);
+            b = c;
+          }
+        }
+        if (steps > STAR_MAX_STEPS) atomicOr(&s_flags, LS_TILE_DEGENERATE);
+        if (hull_b >= 0 && hull_key != FACE_NONE) raster_hull_edge(T, a, hull_b, hull_key, C, R, fm);
+      }
+    }
+    __syncthreads();
+    // ---- e. interpolation, normalisation, output
+    auto lin_value = [&](int tt, double* out4) {
+      const int i = tt / R, j = tt - i * R;
+      const uint64_t f = fm[tt];
+      if (f == FACE_NONE) {
+        const int p = nn[tt];
+        out4[0] = (double)Tz[p] * P.scale_z + P.offset_z;
+        const uint64_t c = Tc[p];
+        out4[1] = (double)(c & 0xFFFF);
+        out4[2] = (double)((c >> 16) & 0xFFFF);
+        out4[3] = (double)((c >> 32) & 0xFFFF);
+        return false;
+      }
+      const int a = (int)(f >> 42), b = (int)((f >> 21) & 0x1FFFFF), c = (int)(f & 0x1FFFFF);
+      const double qx = q0 + j * C, qy = q0 + i * C;
+      const double ob = orient_d(T.u[c], T.v[c], T.u[a], T.v[a], qx, qy);
+      const double oc = orient_d(T.u[a], T.v[a], T.u[b], T.v[b], qx, qy);
+      const double O = orient_d(T.u[a], T.v[a], T.u[b], T.v[b], T.u[c], T.v[c]);
+      const double lb = ob / O, lc = oc / O;
+      const double za = Tz[a], zb = Tz[b], zc = Tz[c];
+      const double h = za + lb * (zb - za) + lc * (zc - za);
+      out4[0] = h * P.scale_z + P.offset_z;
+      const uint64_t ca = Tc[a], cb = Tc[b], cc = Tc[c];
+      for (int ch = 0; ch < 3; ++ch) {
+        const double va = (double)((ca >> (16 * ch)) & 0xFFFF), vb = (double)((cb >> (16 * ch)) & 0xFFFF),
+                     vc = (double)((cc >> (16 * ch)) & 0xFFFF);
+        out4[1 + ch] = va + lb * (vb - va) + lc * (vc - va);
+      }
+      return true;
+    };
+    if (tid == 0) {
+      double v4[4];
+      lin_value((R / 2) * R + R / 2, v4);
+      s_cz = v4[0];
+    }
+    __syncthreads();
+    const double cz = s_cz;
+    float4* __restrict__ out = reinterpret_cast<float4*>(P.x_out + (int64_t)k * RR * 8);
+    for (int tt = tid; tt < RR; tt += RB) {
+      double lv[4];
+      lin_value(tt, lv);
+      const int p = nn[tt];
+      const double hn = (double)Tz[p] * P.scale_z + P.offset_z;
+      const uint64_t c = Tc[p];
+      const double k65 = 1.0 / 65535.0;
+      out[2 * tt] = make_float4((float)((lv[0] - cz) * P.inv_r), (float)((hn - cz) * P.inv_r), (float)(lv[1] * k65),
+                                (float)(lv[2] * k65));
+      out[2 * tt + 1] = make_float4((float)(lv[3] * k65), (float)((double)(c & 0xFFFF) * k65),
+                                    (float)((double)((c >> 16) & 0xFFFF) * k65),
+                                    (float)((double)((c >> 32) & 0xFFFF) * k65));
+    }
+    if (tid == 0) {
+      P.cz_out[k] = cz;
+      int st = flags | s_flags;
+      if (!has_dt) st |= LS_TILE_NN_ONLY;
+      P.status[k] = st;
+    }
+    __syncthreads();
+  }
+}
+
+int g_num_cu = 0;
+
+int num_cus() {
+  if (g_num_cu <= 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    g_num_cu = v;
+  }
+  return g_num_cu;
+}
+
+struct ReconLayout {
+  int32_t* tile_pos;
+  int32_t* counts;
+  int32_t* fill;
+  int32_t* flags;
+  int32_t* queue;
+  int32_t* bin_off;
+  int32_t* bin_idx;
+  int32_t* sort_scratch;
+  int32_t *su, *sv, *sz, *sslot, *tu, *tv, *tz;
+  uint64_t *srgb, *trgb;
+  uint64_t* facemap;
+  int32_t* nnidx;
+  int n_wg;
+  int64_t entries;
+};
+
+int64_t max_multiplicity(const LsGridInfo& gi) {
+  const int64_t per = (2 * (int64_t)gi.H) / gi.S + 1;
+  return per * per;
+}
+
+int recon_wg_count(int32_t n_tiles) {
+  const int want = 2 * num_cus();
+  return n_tiles < want ? (n_tiles > 0 ? n_tiles : 1) : want;
+}
+
+size_t recon_layout(const LsGridInfo& gi, int32_t n_tiles, int64_t n, void* base, ReconLayout* L) {
+  LsArena A{reinterpret_cast<char*>(base), 0, 0};
+  const int64_t nall = (int64_t)gi.tx * gi.ty;
+  const int64_t E = n * max_multiplicity(gi) + 1;
+  const int nwg = recon_wg_count(n_tiles);
+  const int64_t RR = (int64_t)gi.R * gi.R;
+  L->tile_pos = A.take<int32_t>(nall);
+  L->counts = A.take<int32_t>(n_tiles + 1);
+  L->fill = A.take<int32_t>(n_tiles + 1);
+  L->flags = A.take<int32_t>(4);
+  L->queue = L->flags + 1;
+  L->bin_off = A.take<int32_t>(n_tiles + 1);
+  L->bin_idx = A.take<int32_t>(E);
+  L->sort_scratch = A.take<int32_t>(2 * E);
+  L->su = A.take<int32_t>(E);
+  L->sv = A.take<int32_t>(E);
+  L->sz = A.take<int32_t>(E);
+  L->sslot = A.take<int32_t>(E);
+  L->tu = A.take<int32_t>(E);
+  L->tv = A.take<int32_t>(E);
+  L->tz = A.take<int32_t>(E);
+  L->srgb = A.take<uint64_t>(E);
+  L->trgb = A.take<uint64_t>(E);
+  L->facemap = A.take<uint64_t>(RR * nwg);
+  L->nnidx = A.take<int32_t>(RR * nwg);
+  L->n_wg = nwg;
+  L->entries = E;
+  return A.used;
+}
+
+}  // namespace
+
+size_t ls_recon_ws_bytes(const LsGridInfo& gi, int32_t n_tiles, int64_t n) {
+  ReconLayout L;
+  return recon_layout(gi, n_tiles, n, nullptr, &L);
+}
+
+int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                  int64_t n, const int32_t* tile_list, int32_t n_tiles, float* x_out, double* cz_out,
+                  int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
+                  size_t ws_bytes, hipStream_t st) {
+  if (n_tiles <= 0) return LS_OK;
+  ReconLayout L;
+  const size_t need = recon_layout(gi, n_tiles, n, nullptr, &L);
+  if (ws_bytes < need || !ws) return LS_EWORKSPACE;
+  recon_layout(gi, n_tiles, n, ws, &L);
+  const bool user_csr = bin_off && bin_idx;
+  int32_t* boff = user_csr ? bin_off : L.bin_off;
+  int32_t* bidx = user_csr ? bin_idx : L.bin_idx;
+  const int64_t cap = user_csr ? bin_cap : L.entries;
+  const int64_t nall = (int64_t)gi.tx * gi.ty;
+
+  const int T = 256;
+  auto blocks = [&](int64_t cnt) { return (int)std::min<int64_t>((cnt + T - 1) / T, 65535); };
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nall)), dim3(T), 0, st, L.tile_pos, nall, 0x7fffffff);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(n_tiles + 1)), dim3(T), 0, st, L.counts, (int64_t)n_tiles + 1, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(n_tiles + 1)), dim3(T), 0, st, L.fill, (int64_t)n_tiles + 1, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(T), 0, st, L.flags, (int64_t)4, 0);
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks(n_tiles)), dim3(T), 0, st, tile_status, (int64_t)n_tiles, 0);
+  hipLaunchKernelGGL(k_tile_pos, dim3(blocks(n_tiles)), dim3(T), 0, st, tile_list, n_tiles, nall, L.tile_pos,
+                     tile_status);
+  hipLaunchKernelGGL(k_tile_dup, dim3(blocks(n_tiles)), dim3(T), 0, st, tile_list, n_tiles, nall, L.tile_pos,
+                     tile_status);
+  hipLaunchKernelGGL(k_tile_pos_fix, dim3(blocks(nall)), dim3(T), 0, st, L.tile_pos, nall);
+  LS_LAUNCH_CHECK();
+
+  BinParams bp;
+  bp.ox = gi.ox;
+  bp.oy = gi.oy;
+  bp.S = gi.S;
+  bp.H = gi.H;
+  bp.tiles_x = gi.tx;
+  bp.tiles_y = gi.ty;
+  bp.K = 1 + gi.H / gi.S;
+  bp.n_tiles = n_tiles;
+  bp.n = n;
+  bp.x = x;
+  bp.y = y;
+  bp.tile_pos = L.tile_pos;
+  bp.counts = L.counts;
+  bp.fill = L.fill;
+  bp.bin_off = boff;
+  bp.bin_idx = bidx;
+  bp.cap = cap;
+  bp.flags = L.flags;
+  const int pb = (int)std::min<int64_t>((n + T - 1) / T, 8192);
+  if (n > 0) hipLaunchKernelGGL(k_bin_count, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, bp);
+  if (n > 0) hipLaunchKernelGGL(k_bin_scatter, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
+  if (user_csr)
+    hipLaunchKernelGGL(k_bin_sort, dim3(std::min(n_tiles, 4 * num_cus())), dim3(RB), 0, st, boff, n_tiles, bidx,
+                       L.sort_scratch, L.flags);
+  LS_LAUNCH_CHECK();
+
+  ReconParams rp;
+  rp.ox = gi.ox;
+  rp.oy = gi.oy;
+  rp.S = gi.S;
+  rp.tiles_x = gi.tx;
+  rp.C = gi.C;
+  rp.R = gi.R;
+  rp.H = gi.H;
+  rp.scale_z = gi.scale_z;
+  rp.offset_z = gi.offset_z;
+  rp.inv_r = 1.0 / ((double)gi.H * gi.scale_xy);
+  rp.n_tiles = n_tiles;
+  rp.x = x;
+  rp.y = y;
+  rp.z = z;
+  rp.rgb = rgb;
+  rp.tile_list = tile_list;
+  rp.bin_off = boff;
+  rp.bin_idx = bidx;
+  rp.flags = L.flags;
+  rp.su = L.su;
+  rp.sv = L.sv;
+  rp.sz = L.sz;
+  rp.srgb = L.srgb;
+  rp.sslot = L.sslot;
+  rp.tu = L.tu;
+  rp.tv = L.tv;
+  rp.tz = L.tz;
+  rp.trgb = L.trgb;
+  rp.facemap = L.facemap;
+  rp.nnidx = L.nnidx;
+  rp.queue = L.queue;
+  rp.x_out = x_out;
+  rp.cz_out = cz_out;
+  rp.status = tile_status;
+  hipLaunchKernelGGL(k_recon, dim3(L.n_wg), dim3(RB), 0, st, rp);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}

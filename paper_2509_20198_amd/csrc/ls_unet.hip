@@ -1,0 +1,375 @@
+// Refinement network (LidarScout Section 3.4) forward and backward for
+// gfx950: the 3-level U-Net with input-skip head described in lidarscout.h.
+//
+// Every 3x3 convolution reads its input through a ConvSrc descriptor that
+// folds the glue of the network into the load addressing: nearest x2
+// upsampling, channel concatenation of two tensors, embedding a smaller
+// tensor at an offset (the head's crop window, seen from the backward), and
+// the ReLU mask of the backward (a value counts only where the forward
+// activation was positive).  Average pooling writes its own small tensor.
+//
+// FP32 path ("plain"): one launch per layer over the whole batch, each lane
+// one output pixel x COB output channels, weights read as wave-uniform
+// scalars from a [tap][cin][cout] copy.  BF16 path: see ls_unet_bf16.hip.
+#include <algorithm>
+#include <vector>
+
+#include "ls_common.hpp"
+#include "ls_unet.hpp"
+
+namespace {
+
+constexpr int CT = 256;
+
+__global__ void k_prep_weights(const float* __restrict__ w, float* __restrict__ wt, float* __restrict__ wd) {
+  // one thread per weight element of all layers
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t off = 0;
+  for (int l = 0; l < LS_NLAYER; ++l) {
+    const int cin = LS_LAYERS[l].cin, cout = LS_LAYERS[l].cout;
+    const int64_t nw = (int64_t)cout * 9 * cin;
+    if (i >= off && i < off + nw) {
+      const int64_t r = i - off;
+      const int co = (int)(r / (9 * cin));
+      const int tap = (int)((r / cin) % 9);
+      const int ci = (int)(r % cin);
+      const float v = w[i];
+      wt[off + ((int64_t)tap * cin + ci) * cout + co] = v;
+      wd[off + ((int64_t)(8 - tap) * cout + co) * cin + ci] = v;
+      return;
+    }
+    off += nw + cout;
+  }
+}
+
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+// Pixel (yy, xx) of the conv input, channels [c, c+4) of source part `which`.
+template <bool MASK>
+__device__ __forceinline__ float4 src_load4(const ConvSrc& s, int b, int yy, int xx, int c, bool& ok) {
+  const SrcPart& p = c < s.a.c ? s.a : s.b;
+  const int cc = c < s.a.c ? c : c - s.a.c;
+  int sy, sx;
+  if (p.up) {
+    sy = yy >> 1;
+    sx = xx >> 1;
+  } else {
+    sy = yy - p.oy;
+    sx = xx - p.ox;
+  }
+  ok = sy >= 0 && sx >= 0 && sy < p.h && sx < p.w;
+  if (!ok) return make_float4(0.f, 0.f, 0.f, 0.f);
+  const int64_t o = (((int64_t)b * p.h + sy) * p.w + sx) * p.stride + p.coff + cc;
+  float4 v = ld4(p.f32 + o);
+  if (MASK && p.mask) {
+    const float4 m = ld4(p.mask + o);
+    v.x = m.x > 0.f ? v.x : 0.f;
+    v.y = m.y > 0.f ? v.y : 0.f;
+    v.z = m.z > 0.f ? v.z : 0.f;
+    v.w = m.w > 0.f ? v.w : 0.f;
+  }
+  return v;
+}
+
+// Generic FP32 direct conv: out[b][y0+i][x0+j][co] for i < Ho, j < Wo over an
+// H x W input plane with zero padding.
+template <int COB, bool MASK>
+__global__ void __launch_bounds__(CT) k_conv_f32(ConvArgs A) {
+  const int64_t pix = blockIdx.x * (int64_t)CT + threadIdx.x;
+  const int64_t npix = (int64_t)A.B * A.Ho * A.Wo;
+  if (pix >= npix) return;
+  const int b = (int)(pix / ((int64_t)A.Ho * A.Wo));
+  const int r = (int)(pix - (int64_t)b * A.Ho * A.Wo);
+  const int oy = r / A.Wo, ox = r - oy * A.Wo;
+  const int y = A.y0 + oy, x = A.x0 + ox;
+  const int co0 = blockIdx.y * COB;
+  const int cin = A.src.a.c + A.src.b.c;
+  float acc[COB];
+#pragma unroll
+  for (int c = 0; c < COB; ++c) acc[c] = A.bias ? A.bias[co0 + c] : 0.f;
+  for (int ky = 0; ky < 3; ++ky) {
+    const int yy = y + ky - 1;
+    if (yy < 0 || yy >= A.H) continue;
+    for (int kx = 0; kx < 3; ++kx) {
+      const int xx = x + kx - 1;
+      if (xx < 0 || xx >= A.W) continue;
+      const float* wrow = A.wt + (int64_t)(ky * 3 + kx) * cin * A.cout + co0;
+      for (int ci = 0; ci < cin; ci += 4) {
+        bool ok;
+        const float4 v = src_load4<MASK>(A.src, b, yy, xx, ci, ok);
+        if (!ok) continue;
+        const float* w0 = wrow + (int64_t)ci * A.cout;
+#pragma unroll
+        for (int c = 0; c < COB; ++c) {
+          float s = acc[c];
+          s = fmaf(v.x, w0[c], s);
+          s = fmaf(v.y, w0[A.cout + c], s);
+          s = fmaf(v.z, w0[2 * A.cout + c], s);
+          s = fmaf(v.w, w0[3 * A.cout + c], s);
+          acc[c] = s;
+        }
+      }
+    }
+  }
+  float* o = A.out + pix * A.out_stride + A.out_coff + co0;
+#pragma unroll
+  for (int c = 0; c < COB; ++c) o[c] = A.relu ? fmaxf(acc[c], 0.f) : acc[c];
+}
+
+// out = avgpool2x2(in), NHWC, C multiple of 4
+__global__ void k_avgpool_f32(const float* __restrict__ in, float* __restrict__ out, int B, int H, int W, int C) {
+  const int64_t n = (int64_t)B * (H / 2) * (W / 2) * (C / 4);
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c4 = (int)(i % (C / 4));
+  int64_t r = i / (C / 4);
+  const int x = (int)(r % (W / 2));
+  r /= (W / 2);
+  const int y = (int)(r % (H / 2));
+  const int b = (int)(r / (H / 2));
+  const float* p = in + (((int64_t)b * H + 2 * y) * W + 2 * x) * C + 4 * c4;
+  const float4 a = ld4(p), bq = ld4(p + C), c = ld4(p + (int64_t)W * C), d = ld4(p + (int64_t)W * C + C);
+  float4 o;
+  o.x = 0.25f * ((a.x + bq.x) + (c.x + d.x));
+  o.y = 0.25f * ((a.y + bq.y) + (c.y + d.y));
+  o.z = 0.25f * ((a.z + bq.z) + (c.z + d.z));
+  o.w = 0.25f * ((a.w + bq.w) + (c.w + d.w));
+  reinterpret_cast<float4*>(out)[i] = o;
+}
+
+// Head epilogue: y = crop(x[..., {0,2,3,4}]) + head, texture.
+__global__ void k_head_epilogue(const float* __restrict__ head, const float* __restrict__ x, const double* __restrict__ cz,
+                                int B, int res, int pad, double r_m, float* __restrict__ y_out,
+                                float* __restrict__ tex_out) {
+  const int64_t n = (int64_t)B * res * res;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = (int)(i / ((int64_t)res * res));
+  const int r = (int)(i - (int64_t)b * res * res);
+  const int R = res + 2 * pad;
+  const int yy = r / res + pad, xx = r % res + pad;
+  const float* xp = x + (((int64_t)b * R + yy) * R + xx) * 8;
+  const float4 h = ld4(head + 4 * i);
+  const float4 v = make_float4(xp[0] + h.x, xp[2] + h.y, xp[3] + h.z, xp[4] + h.w);
+  if (y_out) reinterpret_cast<float4*>(y_out)[i] = v;
+  if (tex_out) {
+    const double hm = cz[b] + r_m * (double)v.x;
+    reinterpret_cast<float4*>(tex_out)[i] =
+        make_float4((float)hm, fminf(fmaxf(v.y, 0.f), 1.f), fminf(fmaxf(v.z, 0.f), 1.f), fminf(fmaxf(v.w, 0.f), 1.f));
+  }
+}
+
+// ---------------------------------------------------------------- backward
+// dW partials: thread per (weight | bias) element, blockIdx.y = pixel chunk.
+// dZ(p, co) = dA[p][co] * (A[p][co] > 0) (mask optional), defined on the
+// output window; the input is read through the forward ConvSrc.
+__global__ void __launch_bounds__(CT) k_wgrad_f32(WgradArgs A) {
+  const int cin = A.src.a.c + A.src.b.c;
+  const int64_t nw = (int64_t)A.cout * 9 * cin;
+  const int64_t idx = blockIdx.x * (int64_t)CT + threadIdx.x;
+  if (idx >= nw + A.cout) return;
+  const int64_t npix = (int64_t)A.B * A.Ho * A.Wo;
+  const int64_t p0 = npix * blockIdx.y / gridDim.y, p1 = npix * (blockIdx.y + 1) / gridDim.y;
+  float acc = 0.f;
+  if (idx < nw) {
+    const int co = (int)(idx / (9 * cin));
+    const int tap = (int)((idx / cin) % 9);
+    const int ci = (int)(idx % cin);
+    const int ky = tap / 3, kx = tap % 3;
+    const bool in_a = ci < A.src.a.c;
+    const SrcPart& sp = in_a ? A.src.a : A.src.b;
+    const int cc = in_a ? ci : ci - A.src.a.c;
+    for (int64_t p = p0; p < p1; ++p) {
+      float g = A.dA[p * A.d_stride + co];
+      if (A.mask && !(A.mask[p * A.d_stride + co] > 0.f)) g = 0.f;
+      if (g == 0.f) continue;
+      const int b = (int)(p / ((int64_t)A.Ho * A.Wo));
+      const int r = (int)(p - (int64_t)b * A.Ho * A.Wo);
+      const int yy = A.y0 + r / A.Wo + ky - 1, xx = A.x0 + r % A.Wo + kx - 1;
+      if (yy < 0 || yy >= A.H || xx < 0 || xx >= A.W) continue;
+      int sy, sx;
+      if (sp.up) {
+        sy = yy >> 1;
+        sx = xx >> 1;
+      } else {
+        sy = yy - sp.oy;
+        sx = xx - sp.ox;
+      }
+      if (sy < 0 || sx < 0 || sy >= sp.h || sx >= sp.w) continue;
+      acc = fmaf(g, sp.f32[(((int64_t)b * sp.h + sy) * sp.w + sx) * sp.stride + sp.coff + cc], acc);
+    }
+  } else {
+    const int co = (int)(idx - nw);
+    for (int64_t p = p0; p < p1; ++p) {
+      float g = A.dA[p * A.d_stride + co];
+      if (A.mask && !(A.mask[p * A.d_stride + co] > 0.f)) g = 0.f;
+      acc += g;
+    }
+  }
+  A.partial[(int64_t)blockIdx.y * (nw + A.cout) + idx] = acc;
+}
+
+__global__ void k_reduce_partials(const float* __restrict__ partial, int nchunk, int64_t n, float* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * n + i];
+  out[i] = s;
+}
+
+// dLow[b][y][x][c] = sum of the 2x2 block of dHigh (first `c_low` channels of
+// a `stride`-channel tensor): adjoint of nearest x2 upsampling.
+__global__ void k_up_adjoint(const float* __restrict__ dhigh, int stride, float* __restrict__ dlow, int B, int h, int w,
+                             int c_low) {
+  const int64_t n = (int64_t)B * h * w * c_low;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)(i % c_low);
+  int64_t r = i / c_low;
+  const int x = (int)(r % w);
+  r /= w;
+  const int y = (int)(r % h);
+  const int b = (int)(r / h);
+  const int W = 2 * w;
+  const float* p = dhigh + (((int64_t)b * 2 * h + 2 * y) * W + 2 * x) * stride + c;
+  dlow[i] = (p[0] + p[stride]) + (p[(int64_t)W * stride] + p[(int64_t)W * stride + stride]);
+}
+
+// dst[p][c] = (accumulate ? dst : 0) + src[p*stride + coff + c]
+__global__ void k_copy_channels(const float* __restrict__ src, int stride, int coff, float* __restrict__ dst, int C,
+                                int64_t npix, int accumulate) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= npix * C) return;
+  const int64_t p = i / C;
+  const int c = (int)(i - p * C);
+  const float v = src[p * stride + coff + c];
+  dst[i] = accumulate ? dst[i] + v : v;
+}
+
+// dHigh += 0.25 * spread(dLow): adjoint of 2x2 average pooling
+__global__ void k_pool_adjoint_add(const float* __restrict__ dlow, float* __restrict__ dhigh, int B, int H, int W, int C) {
+  const int64_t n = (int64_t)B * H * W * C;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c = (int)(i % C);
+  int64_t r = i / C;
+  const int x = (int)(r % W);
+  r /= W;
+  const int y = (int)(r % H);
+  const int b = (int)(r / H);
+  dhigh[i] += 0.25f * dlow[(((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+}
+
+// dX[crop][{0,2,3,4}] += dY (residual path)
+__global__ void k_residual_adjoint(const float* __restrict__ dy, float* __restrict__ dx, int B, int res, int pad) {
+  const int64_t n = (int64_t)B * res * res;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = (int)(i / ((int64_t)res * res));
+  const int r = (int)(i - (int64_t)b * res * res);
+  const int R = res + 2 * pad;
+  float* p = dx + (((int64_t)b * R + r / res + pad) * R + r % res + pad) * 8;
+  const float4 g = ld4(dy + 4 * i);
+  p[0] += g.x;
+  p[2] += g.y;
+  p[3] += g.z;
+  p[4] += g.w;
+}
+
+inline int nblk(int64_t n) { return (int)((n + CT - 1) / CT); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+SrcPart src_plain(const float* p, int c, int h, int w, int stride, int coff, const float* mask) {
+  SrcPart s;
+  s.f32 = p;
+  s.bf16 = nullptr;
+  s.mask = mask;
+  s.c = c;
+  s.h = h;
+  s.w = w;
+  s.stride = stride;
+  s.coff = coff;
+  s.up = 0;
+  s.oy = 0;
+  s.ox = 0;
+  return s;
+}
+
+SrcPart src_none() { return src_plain(nullptr, 0, 0, 0, 0, 0, nullptr); }
+
+int ls_conv_f32(const ConvArgs& a, hipStream_t st) {
+  const int64_t npix = (int64_t)a.B * a.Ho * a.Wo;
+  const bool mask = (a.src.a.mask != nullptr) || (a.src.b.mask != nullptr);
+  const int cob = a.cout % 32 == 0 ? 32 : (a.cout % 16 == 0 ? 16 : (a.cout % 8 == 0 ? 8 : 4));
+  if (a.cout % 4) return LS_ENOTIMPL;
+  dim3 grid(nblk(npix), a.cout / cob);
+#define LS_CONV_CASE(N)                                                                   \
+  if (cob == N) {                                                                          \
+    if (mask) hipLaunchKernelGGL((k_conv_f32<N, true>), grid, dim3(CT), 0, st, a);         \
+    else hipLaunchKernelGGL((k_conv_f32<N, false>), grid, dim3(CT), 0, st, a);             \
+  }
+  LS_CONV_CASE(32) LS_CONV_CASE(16) LS_CONV_CASE(8) LS_CONV_CASE(4)
+#undef LS_CONV_CASE
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_avgpool_f32(const float* in, float* out, int B, int H, int W, int C, hipStream_t st) {
+  const int64_t n = (int64_t)B * (H / 2) * (W / 2) * (C / 4);
+  hipLaunchKernelGGL(k_avgpool_f32, dim3(nblk(n)), dim3(CT), 0, st, in, out, B, H, W, C);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_head_epilogue(const float* head, const float* x, const double* cz, int B, int res, int pad, double r_m,
+                     float* y_out, float* tex_out, hipStream_t st) {
+  const int64_t n = (int64_t)B * res * res;
+  hipLaunchKernelGGL(k_head_epilogue, dim3(nblk(n)), dim3(CT), 0, st, head, x, cz, B, res, pad, r_m, y_out, tex_out);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_prep_weights(const float* w, float* wt, float* wd, hipStream_t st) {
+  hipLaunchKernelGGL(k_prep_weights, dim3(nblk(LS_NUM_PARAMS)), dim3(CT), 0, st, w, wt, wd);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st) {
+  const int cin = a.src.a.c + a.src.b.c;
+  const int64_t n = (int64_t)a.cout * 9 * cin + a.cout;
+  dim3 grid(nblk(n), a.nchunk);
+  hipLaunchKernelGGL(k_wgrad_f32, grid, dim3(CT), 0, st, a);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nblk(n)), dim3(CT), 0, st, a.partial, a.nchunk, n, grad_w_layer);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_up_adjoint(const float* dhigh, int stride, float* dlow, int B, int h, int w, int c_low, hipStream_t st) {
+  const int64_t n = (int64_t)B * h * w * c_low;
+  hipLaunchKernelGGL(k_up_adjoint, dim3(nblk(n)), dim3(CT), 0, st, dhigh, stride, dlow, B, h, w, c_low);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_copy_channels(const float* src, int stride, int coff, float* dst, int C, int64_t npix, int acc, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_channels, dim3(nblk(npix * C)), dim3(CT), 0, st, src, stride, coff, dst, C, npix, acc);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_pool_adjoint_add(const float* dlow, float* dhigh, int B, int H, int W, int C, hipStream_t st) {
+  const int64_t n = (int64_t)B * H * W * C;
+  hipLaunchKernelGGL(k_pool_adjoint_add, dim3(nblk(n)), dim3(CT), 0, st, dlow, dhigh, B, H, W, C);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_residual_adjoint(const float* dy, float* dx, int B, int res, int pad, hipStream_t st) {
+  const int64_t n = (int64_t)B * res * res;
+  hipLaunchKernelGGL(k_residual_adjoint, dim3(nblk(n)), dim3(CT), 0, st, dy, dx, B, res, pad);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}

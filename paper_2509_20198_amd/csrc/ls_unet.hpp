@@ -1,0 +1,60 @@
+// Internal interfaces of the refinement-network kernels.
+#pragma once
+
+#include "ls_common.hpp"
+
+// One stored tensor seen as (part of) a conv input.
+struct SrcPart {
+  const float* f32;      // FP32 storage (FP32 path, and the network input x)
+  const uint16_t* bf16;  // BF16 storage (BF16 path); exactly one of f32/bf16 is set
+  const float* mask;     // FP32 backward: zero the value where mask <= 0 (same layout)
+  int c;                 // channels taken from this part
+  int h, w;              // stored spatial size
+  int stride;            // channels per stored pixel
+  int coff;              // first channel within the stored pixel
+  int up;                // nearest x2 upsampling: stored at half resolution
+  int oy, ox;            // embedding: stored (sy, sx) sits at input (sy + oy, sx + ox)
+};
+
+// Conv input: channels [0, a.c) from part a, [a.c, a.c + b.c) from part b.
+struct ConvSrc {
+  SrcPart a, b;
+};
+
+struct ConvArgs {
+  ConvSrc src;
+  int B, H, W;           // batch and input plane (zero padding outside)
+  int y0, x0, Ho, Wo;    // output window inside the plane
+  const float* wt;       // [9][cin][cout] weights of this layer
+  const float* bias;     // [cout] or null
+  int cout;
+  int relu;
+  float* out;            // [B][Ho][Wo][out_stride]
+  int out_stride, out_coff;
+};
+
+struct WgradArgs {
+  ConvSrc src;
+  int B, H, W;
+  int y0, x0, Ho, Wo;
+  int cout;
+  const float* dA;       // gradient at the conv output, [B][Ho][Wo][d_stride]
+  const float* mask;     // forward activation (ReLU mask) or null, same layout
+  int d_stride;
+  float* partial;        // [nchunk][cout*9*cin + cout]
+  int nchunk;
+};
+
+SrcPart src_plain(const float* p, int c, int h, int w, int stride, int coff, const float* mask);
+SrcPart src_none();
+
+int ls_conv_f32(const ConvArgs& a, hipStream_t st);
+int ls_avgpool_f32(const float* in, float* out, int B, int H, int W, int C, hipStream_t st);
+int ls_head_epilogue(const float* head, const float* x, const double* cz, int B, int res, int pad, double r_m,
+                     float* y_out, float* tex_out, hipStream_t st);
+int ls_prep_weights(const float* w, float* wt, float* wd, hipStream_t st);
+int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st);
+int ls_up_adjoint(const float* dhigh, int stride, float* dlow, int B, int h, int w, int c_low, hipStream_t st);
+int ls_copy_channels(const float* src, int stride, int coff, float* dst, int C, int64_t npix, int acc, hipStream_t st);
+int ls_pool_adjoint_add(const float* dlow, float* dhigh, int B, int H, int W, int C, hipStream_t st);
+int ls_residual_adjoint(const float* dy, float* dx, int B, int res, int pad, hipStream_t st);

@@ -1,0 +1,170 @@
+"""GPU parity: binning CSR (bit-exact), nearest-neighbour maps (exact) and
+Delaunay-linear maps (<= 1e-4 m) of ls_recon_tiles against the FP64 oracle
+(Algorithm 1 and the Section 3.4 normalisation)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_20198_amd as ls
+import synth
+from gpu_helpers import R_M, arrays_to_dev, points_to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_M = 1e-4
+
+
+def _gpu_recon(region, ps_np, tile_list, want_csr=True):
+    g = ls.Grid.of(region)
+    xt, yt, zt, rt = arrays_to_dev(*ps_np)
+    tl = torch.from_numpy(np.ascontiguousarray(tile_list, np.int32)).cuda()
+    nt = len(tile_list)
+    if want_csr:
+        off = torch.empty(nt + 1, dtype=torch.int32, device="cuda")
+        idx = torch.empty(max(4 * len(ps_np[0]), 1), dtype=torch.int32, device="cuda")
+        xo, cz, st = ls.recon_tiles(g, xt, yt, zt, rt, tl, bin_off=off, bin_idx=idx)
+    else:
+        off = idx = None
+        xo, cz, st = ls.recon_tiles(g, xt, yt, zt, rt, tl)
+    torch.cuda.synchronize()
+    out = dict(x=xo.cpu().numpy().astype(np.float64), cz=cz.cpu().numpy(), status=st.cpu().numpy())
+    if want_csr:
+        o = off.cpu().numpy()
+        out["off"] = o
+        out["idx"] = idx.cpu().numpy()[: o[-1]]
+    return out
+
+
+def _compare(region, ps_np, tile_list, gpu=None):
+    x, y, z, rgb = ps_np
+    xo, cz, st = oracle.recon_tiles(region, x, y, z, rgb, tile_list)
+    gpu = gpu or _gpu_recon(region, ps_np, tile_list)
+    off, idx = oracle.bin_points(region, x, y, tile_list)
+    if "off" in gpu:
+        assert np.array_equal(gpu["off"], off)
+        assert np.array_equal(gpu["idx"], idx)
+    r = R_M * region.scale_xy / 0.01 if region.pad == 16 else (region.tile_size / 2 + region.pad * region.cell) * region.scale_xy
+    np.testing.assert_allclose(gpu["cz"], cz, rtol=0, atol=1e-9)
+    # heights in metres: linear within 1e-4 m, nearest neighbour exact up to FP32 rounding of x
+    err_lin = np.abs(gpu["x"][..., 0] - xo[..., 0]).max() * r
+    err_nn = np.abs(gpu["x"][..., 1] - xo[..., 1]).max() * r
+    assert err_lin <= TOL_M, err_lin
+    assert err_nn <= 1e-6 * max(1.0, np.abs(xo[..., 1]).max() * r), err_nn
+    # colours: NN exact (integer colour), linear within 1e-5 of [0, 1]
+    assert np.array_equal(np.rint(gpu["x"][..., 5:8] * 65535), np.rint(xo[..., 5:8] * 65535))
+    assert np.abs(gpu["x"][..., 2:5] - xo[..., 2:5]).max() <= 1e-5
+    assert np.array_equal(gpu["status"] & 3, st)
+    return gpu, (xo, cz, st)
+
+
+def test_single_tile_400():
+    w = synth.single_tile(seed=1, n=400)
+    _compare(w.region, w.points.numpy(), w.tile_list)
+
+
+@pytest.mark.parametrize("seed", [2, 3])
+def test_batch_6x6_loguniform(seed):
+    w = synth.batch_tiles(seed=seed, tiles_x=6, tiles_y=6)
+    _compare(w.region, w.points.numpy(), w.tile_list)
+
+
+def test_subset_tile_list_and_pad0():
+    w = synth.batch_tiles(seed=4, tiles_x=5, tiles_y=4, pad=0)
+    tl = np.array([7, 3, 19, 0, 12], np.int32)
+    _compare(w.region, w.points.numpy(), tl)
+
+
+def test_pareto_counts_small_tiles():
+    counts = synth.counts_pareto(6, 64)
+    w = synth.sparse_workload("pareto", 8, 8, counts, 6, order="id")
+    _compare(w.region, w.points.numpy(), w.tile_list)
+
+
+def test_edge_cases_empty_nn_only_duplicates():
+    region = synth.Region(tiles_x=4, tiles_y=1)
+    S = 64000
+    # tile 0: empty window (no points near), tile 1: 1 point, tile 2: 2 points + collinear triple nearby
+    # tile 3: duplicates (same xy, different z/colour)
+    xs = [S + 32000, 2 * S + 100, 2 * S + 900, 2 * S + 1700, 3 * S + 5000, 3 * S + 5000, 3 * S + 5000,
+          3 * S + 20000, 3 * S + 40000]
+    ys = [32000, 10000, 10800, 11600, 30000, 30000, 30000, 50000, 12345]
+    zs = [100, 200, 300, 400, 500, 700, 700, 800, 900]
+    rgb = np.array([[1, 2, 3]] * 5 + [[9, 9, 9], [9, 9, 10], [4, 4, 4], [5, 5, 5]], np.uint16) * 257
+    # move tile 1's point so tile 0's window (reaching 160 m into tile 1) stays empty
+    xs[0] = S + 40000
+    ps = (np.array(xs, np.int32), np.array(ys, np.int32), np.array(zs, np.int32), rgb)
+    gpu, (xo, cz, st) = _compare(region, ps, np.arange(4, dtype=np.int32))
+    assert st[0] == oracle.ORA_EMPTY and (gpu["status"][0] & ls.TILE_EMPTY)
+    assert np.all(gpu["x"][0] == 0)
+
+
+def test_bad_and_duplicate_tile_ids():
+    w = synth.batch_tiles(seed=9, tiles_x=3, tiles_y=3)
+    tl = np.array([4, 4, 99, 1], np.int32)
+    gpu = _gpu_recon(w.region, w.points.numpy(), tl, want_csr=False)
+    assert gpu["status"][1] & ls.TILE_BADID and gpu["status"][2] & ls.TILE_BADID
+    assert not gpu["status"][0] & ls.TILE_BADID and not gpu["status"][3] & ls.TILE_BADID
+    assert np.all(gpu["x"][1] == 0) and np.all(gpu["x"][2] == 0)
+    xo, cz, st = oracle.recon_tiles(w.region, *w.points.numpy(), np.array([4, 1], np.int32))
+    assert np.abs(gpu["x"][[0, 3]] - xo).max() * R_M <= TOL_M
+
+
+def test_cap_too_small_flags_every_tile():
+    w = synth.batch_tiles(seed=10, tiles_x=2, tiles_y=2)
+    g = ls.Grid.of(w.region)
+    xt, yt, zt, rt = points_to_dev(w.points)
+    tl = torch.from_numpy(w.tile_list).cuda()
+    off = torch.empty(5, dtype=torch.int32, device="cuda")
+    idx = torch.empty(10, dtype=torch.int32, device="cuda")
+    xo, cz, st = ls.recon_tiles(g, xt, yt, zt, rt, tl, bin_off=off, bin_idx=idx)
+    torch.cuda.synchronize()
+    o, _ = oracle.bin_points(w.region, *w.points.numpy()[:2], w.tile_list)
+    assert int(off[-1].item()) == o[-1]
+    assert np.all(st.cpu().numpy() & ls.TILE_CAP)
+
+
+def test_planar_reproduction_lattice():
+    """Cocircular lattice points: every triangulation reproduces a plane."""
+    region = synth.Region()
+    rng = np.random.default_rng(7)
+    H = 48000
+    gsel = rng.choice(960 * 960, 3000, replace=False)
+    u = np.concatenate([(gsel % 960) * 100 - H, [-H, H - 100, -H, H - 100]])
+    v = np.concatenate([(gsel // 960) * 100 - H, [-H, -H, H - 100, H - 100]])
+    z = (3 * u - 2 * v) // 100 + 500
+    ps = ((u + 32000).astype(np.int32), (v + 32000).astype(np.int32), z.astype(np.int32),
+          np.zeros((len(u), 3), np.uint16))
+    gpu = _gpu_recon(region, ps, np.zeros(1, np.int32), want_csr=False)
+    c = -H + 500 + 1000 * np.arange(96)
+    qx, qy = np.meshgrid(c, c)
+    plane = ((3 * qx - 2 * qy) / 100 + 500) * 0.01
+    h = gpu["x"][0, ..., 0] * R_M + gpu["cz"][0]
+    assert np.abs(h - plane).max() <= TOL_M
+    assert gpu["status"][0] == 0
+
+
+def test_deterministic_and_order_independent():
+    w = synth.batch_tiles(seed=11, tiles_x=4, tiles_y=4)
+    ps = w.points.numpy()
+    a = _gpu_recon(w.region, ps, w.tile_list)
+    b = _gpu_recon(w.region, ps, w.tile_list)
+    perm = np.random.default_rng(0).permutation(len(ps[0]))
+    c = _gpu_recon(w.region, tuple(p[perm] for p in ps), w.tile_list, want_csr=False)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["idx"], b["idx"])
+    assert np.array_equal(a["x"], c["x"])
+
+
+def test_full_batch_1024_sampled():
+    """The 1024-tile batch in the launch configuration the benchmark uses;
+    the oracle checks a sample of tiles one by one."""
+    w = synth.batch_tiles(seed=2)
+    ps = w.points.numpy()
+    gpu = _gpu_recon(w.region, ps, w.tile_list, want_csr=False)
+    rng = np.random.default_rng(1)
+    ks = np.concatenate([[0, 1, len(w.tile_list) - 1], rng.choice(len(w.tile_list), 9, replace=False)])
+    xo, cz, st = oracle.recon_tiles(w.region, *ps, w.tile_list[ks])
+    assert np.abs(gpu["x"][ks][..., 0] - xo[..., 0]).max() * R_M <= TOL_M
+    assert np.abs(gpu["x"][ks][..., 1] - xo[..., 1]).max() * R_M <= 1e-5
+    np.testing.assert_allclose(gpu["cz"][ks], cz, atol=1e-9)
+    assert np.all(gpu["status"] == 0)

@@ -1,0 +1,144 @@
+"""GPU parity: refinement network forward (FP32 within 1e-4 m, BF16 within
+0.05 m RMS per tile against the FP64 oracle) and backward (FP32 within 1e-3
+relative of the oracle gradient), Section 3.4."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2509_20198_amd as ls
+import synth
+from gpu_helpers import R_M, rms_per_tile
+
+pytestmark = pytest.mark.gpu
+
+
+def _x_from_oracle(n_tiles_side=3, seed=2):
+    w = synth.batch_tiles(seed=seed, tiles_x=n_tiles_side, tiles_y=n_tiles_side)
+    xo, cz, st = oracle.recon_tiles(w.region, *w.points.numpy(), w.tile_list)
+    return w, xo, cz
+
+
+def _run(w, xo, cz, wts, precision):
+    g = ls.Grid.of(w.region)
+    xt = torch.from_numpy(xo.astype(np.float32)).cuda()
+    czt = torch.from_numpy(cz).cuda()
+    wt = torch.from_numpy(wts.astype(np.float32)).cuda()
+    wb = ls.pack_weights_bf16(wt) if precision == ls.BF16 else None
+    y, tex = ls.refine_tiles(wt, xt, czt, g, precision, w_bf16=wb)
+    torch.cuda.synchronize()
+    return y.cpu().numpy().astype(np.float64), tex.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("bias_std", [0.0, 0.05])
+def test_forward_fp32(bias_std):
+    w, xo, cz = _x_from_oracle()
+    wts = synth.unet_weights(0, bias_std=bias_std)
+    y, tex = _run(w, xo.astype(np.float32).astype(np.float64), cz, wts, ls.FP32)
+    x32 = xo.astype(np.float32).astype(np.float64)
+    y_ref = oracle.unet_forward(wts.astype(np.float32).astype(np.float64), x32, 64, 16)
+    tex_ref = oracle.texture(y_ref, cz, w.region)
+    assert np.abs(tex[..., 0] - tex_ref[..., 0]).max() <= 1e-4
+    assert np.abs(y - y_ref).max() <= 1e-6
+    assert np.abs(tex[..., 1:] - tex_ref[..., 1:]).max() <= 1e-5
+
+
+def test_forward_fp32_large_head_pad0():
+    """A larger head (outputs far from the residual) and the unpadded grid."""
+    w = synth.batch_tiles(seed=5, tiles_x=2, tiles_y=2, pad=0)
+    xo, cz, st = oracle.recon_tiles(w.region, *w.points.numpy(), w.tile_list)
+    wts = synth.unet_weights(3, head_std=0.05, bias_std=0.05)
+    y, _ = _run(w, xo, cz, wts, ls.FP32)
+    y_ref = oracle.unet_forward(wts.astype(np.float32).astype(np.float64), xo.astype(np.float32).astype(np.float64),
+                                64, 0)
+    assert np.abs(y - y_ref).max() * 320.0 <= 1e-4
+
+
+def test_zero_head_is_linear_baseline():
+    w, xo, cz = _x_from_oracle(2)
+    wts = synth.unet_weights(0)
+    off = sum(co * 9 * ci + co for _, ci, co in synth.UNET_SHAPES[:-1])
+    wts[off:] = 0
+    for prec in (ls.FP32, ls.BF16):
+        y, _ = _run(w, xo, cz, wts, prec)
+        assert np.array_equal(y, xo.astype(np.float32)[:, 16:80, 16:80][..., [0, 2, 3, 4]].astype(np.float64))
+
+
+def test_forward_bf16_rms_gate():
+    w, xo, cz = _x_from_oracle(4)
+    wts = synth.unet_weights(0)
+    _, tex = _run(w, xo, cz, wts, ls.BF16)
+    y_ref = oracle.unet_forward(wts, xo, 64, 16)
+    tex_ref = oracle.texture(y_ref, cz, w.region)
+    rms = rms_per_tile(tex[..., 0], tex_ref[..., 0])
+    delta = rms_per_tile(tex_ref[..., 0], oracle.texture(xo[:, 16:80, 16:80][..., [0, 2, 3, 4]], cz, w.region)[..., 0])
+    print(f"bf16 per-tile RMS max {rms.max():.4f} m (head RMS {delta.mean():.3f} m)")
+    assert rms.max() <= 0.05
+    assert delta.mean() > 0.5  # the head contributes metres, so the gate is not vacuous
+
+
+def _backward_case(precision, n=3, want_gx=True):
+    w, xo, cz = _x_from_oracle(2, seed=7)
+    xo = xo[:n]
+    wts = synth.unet_weights(1, head_std=0.05, bias_std=0.05)
+    rng = np.random.default_rng(3)
+    G = rng.standard_normal((xo.shape[0], 64, 64, 4))
+    g = ls.Grid.of(w.region)
+    xt = torch.from_numpy(xo.astype(np.float32)).cuda()
+    wt = torch.from_numpy(wts.astype(np.float32)).cuda()
+    gt = torch.from_numpy(G.astype(np.float32)).cuda()
+    wb = ls.pack_weights_bf16(wt) if precision == ls.BF16 else None
+    gw, gx = ls.refine_backward(wt, xt, gt, g, precision, w_bf16=wb, want_grad_x=want_gx)
+    torch.cuda.synchronize()
+    return w, xo, wts, G, g, xt, wt, gt, wb, gw.cpu().numpy().astype(np.float64), \
+        (gx.cpu().numpy().astype(np.float64) if gx is not None else None)
+
+
+def test_backward_fp32_matches_oracle():
+    w, xo, wts, G, *_, gw, gx = _backward_case(ls.FP32)
+    x32 = xo.astype(np.float32).astype(np.float64)
+    gw_ref, gx_ref = oracle.unet_backward(wts.astype(np.float32).astype(np.float64), x32, G, 64, 16, want_gx=True)
+    rel = np.linalg.norm(gw - gw_ref) / np.linalg.norm(gw_ref)
+    relx = np.linalg.norm(gx - gx_ref) / np.linalg.norm(gx_ref)
+    print(f"fp32 backward rel err w {rel:.2e} x {relx:.2e}")
+    assert rel <= 1e-3 and relx <= 1e-3
+    off = 0
+    for name, ci, co in synth.UNET_SHAPES:  # every layer, not just the norm
+        sz = co * 9 * ci + co
+        r = np.linalg.norm(gw[off:off + sz] - gw_ref[off:off + sz]) / max(np.linalg.norm(gw_ref[off:off + sz]), 1e-30)
+        assert r <= 1e-3, (name, r)
+        off += sz
+
+
+def test_backward_saved_activations_equal_recompute():
+    w, xo, wts, G, g, xt, wt, gt, wb, gw, gx = _backward_case(ls.FP32, want_gx=False)
+    act = torch.empty(ls.act_bytes(g, xt.shape[0], ls.FP32), dtype=torch.uint8, device="cuda")
+    ls.refine_tiles(wt, xt, None, g, ls.FP32, act_save=act, want_tex=False)
+    gw2, _ = ls.refine_backward(wt, xt, gt, g, ls.FP32, act_save=act)
+    torch.cuda.synchronize()
+    assert np.array_equal(gw2.cpu().numpy().astype(np.float64), gw)
+
+
+def test_full_batch_1024_bf16_and_fp32_sampled():
+    """Recon + refine over the 1024-tile batch in the benchmark's launch
+    configuration; the FP64 oracle checks a sample of tiles."""
+    w = synth.batch_tiles(seed=2)
+    ps = w.points
+    g = ls.Grid.of(w.region)
+    xt, yt, zt = (t.cuda() for t in (ps.x, ps.y, ps.z))
+    rt = ps.rgb_u16().cuda()
+    tl = torch.from_numpy(w.tile_list).cuda()
+    xo, cz, st = ls.recon_tiles(g, xt, yt, zt, rt, tl)
+    wts = synth.unet_weights(0)
+    wt = torch.from_numpy(wts.astype(np.float32)).cuda()
+    wb = ls.pack_weights_bf16(wt)
+    _, tex32 = ls.refine_tiles(wt, xo, cz, g, ls.FP32, want_y=False)
+    _, tex16 = ls.refine_tiles(wt, xo, cz, g, ls.BF16, w_bf16=wb, want_y=False)
+    torch.cuda.synchronize()
+    ks = np.array([0, 5, 500, 1023])
+    xr, czr, _ = oracle.recon_tiles(w.region, *ps.numpy(), w.tile_list[ks])
+    ref = oracle.texture(oracle.unet_forward(wts, xr, 64, 16), czr, w.region)
+    t32 = tex32.cpu().numpy()[ks].astype(np.float64)
+    t16 = tex16.cpu().numpy()[ks].astype(np.float64)
+    assert np.abs(t32[..., 0] - ref[..., 0]).max() <= 1e-4
+    assert rms_per_tile(t16[..., 0], ref[..., 0]).max() <= 0.05
