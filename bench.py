@@ -1,0 +1,313 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-tile heightmap hot path on one MI355X.
+
+A step is one pass of the whole reconstruction over the 1024-tile batch
+(32 x 32 tiles of 640 m, 50-2000 sparse points per tile, log-uniform, the
+same fBm terrain with per-tile seeds): tile binning, Algorithm 1 (nearest +
+Delaunay-linear maps), normalisation and the refinement network with BF16
+matrix-core convolutions, all captured in one HIP graph and replayed.  The
+plain FP32 path (one launch per layer, no graph) is timed on the same
+inputs for the comparison the metric asks for.
+
+Printed: one JSON line.  `value` is BF16-batched tiles/s with inputs
+resident in HBM.  `roofline` is for the dominant kernel group, timed live
+with HIP events on its own stream; `cpu_baseline` is the FP64 oracle on a
+bounded, strided sample of the same tiles (it also supplies the per-tile
+error of the GPU result).  Secondary figures: the full-resolution splat
+(100 M Morton-ordered points over 64 x 64 tiles) and the refinement backward
+(256 tiles).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import paper_2509_20198_amd as ls  # noqa: E402
+import synth  # noqa: E402
+
+METRIC = "heightmap tiles/s, BF16 batched vs FP32 plain at ≤0.05 m RMS vs FP64 oracle"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def unet_flops(res: int, pad: int) -> float:
+    """Multiply-add FLOPs (x2) of one tile's forward: every 3x3 conv on its
+    plane, the head only on the res x res crop."""
+    R = res + 2 * pad
+    planes = [R, R, R // 2, R // 2, R // 4, R // 4, R // 2, R // 2, R, R]
+    total = 0
+    for (name, ci, co), hw in zip(synth.UNET_SHAPES[:-1], planes):
+        total += 2 * hw * hw * co * 9 * ci
+    _, ci, co = synth.UNET_SHAPES[-1]
+    total += 2 * res * res * co * 9 * ci
+    return float(total)
+
+
+class Timer:
+    def __init__(self):
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+
+    def run(self, fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        self.a.record()
+        for _ in range(steps):
+            fn()
+        self.b.record()
+        torch.cuda.synchronize()
+        return self.a.elapsed_time(self.b) / steps
+
+
+def cpu_baseline(work, sample_idx, gpu_tex_bf16, gpu_tex_fp32, weights64):
+    """The FP64 oracle (recon + network forward) on a strided sample of the
+    batch, timed on the host cores; also the GPU error on those tiles."""
+    import oracle
+
+    nthreads = oracle.default_threads()
+    x, y, z, rgb = work.points.numpy()
+    tl = work.tile_list[sample_idx]
+    t0 = time.perf_counter()
+    xo, cz, _ = oracle.recon_tiles(work.region, x, y, z, rgb, tl, nthreads=nthreads)
+    yo = oracle.unet_forward(weights64, xo, work.region.res, work.region.pad, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    tex = oracle.texture(yo, cz, work.region)
+    d16 = gpu_tex_bf16[..., 0].astype(np.float64) - tex[..., 0]
+    d32 = gpu_tex_fp32[..., 0].astype(np.float64) - tex[..., 0]
+    rms16 = np.sqrt((d16 ** 2).reshape(len(tl), -1).mean(1))
+    base = oracle.texture(xo[:, work.region.pad:work.region.pad + work.region.res,
+                             work.region.pad:work.region.pad + work.region.res][..., [0, 2, 3, 4]], cz, work.region)
+    head_rms = np.sqrt(((tex[..., 0] - base[..., 0]) ** 2).reshape(len(tl), -1).mean(1))
+    return {
+        "value": len(tl) / dt,
+        "unit": "tiles/s",
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": f"{len(tl)} tiles (every {len(work.tile_list) // len(tl)}th of the batch): FP64 binning, "
+                  f"Algorithm 1, normalisation and network forward; wall {dt:.2f} s",
+    }, {
+        "bf16_rms_max_m": float(rms16.max()),
+        "bf16_rms_mean_m": float(rms16.mean()),
+        "bf16_abs_p99_m": float(np.quantile(np.abs(d16), 0.99)),
+        "fp32_max_abs_m": float(np.abs(d32).max()),
+        "head_rms_mean_m": float(head_rms.mean()),
+        "tiles_checked": len(tl),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-tiles", type=int, default=64, help="oracle sample size (0 = skip)")
+    ap.add_argument("--no-secondary", action="store_true", help="skip splat / backward figures")
+    ap.add_argument("--splat-points", type=int, default=100_000_000)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the per-tile path needs no collective and this build runs on a "
+              "single MI355X; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ls.load_library()
+
+    # ---------------------------------------------------------------- inputs
+    work = synth.batch_tiles(seed=2, device=dev)
+    region = work.region
+    g = ls.Grid.of(region)
+    ps = work.points
+    nt = len(work.tile_list)
+    x, y, z = ps.x.contiguous(), ps.y.contiguous(), ps.z.contiguous()
+    rgb = ps.rgb_u16()
+    tl = torch.from_numpy(work.tile_list).to(dev)
+    w64 = synth.unet_weights(0)
+    w = torch.from_numpy(w64.astype(np.float32)).to(dev)
+    wb = ls.pack_weights_bf16(w)
+    R, res = g.R, g.res
+    x_out = torch.empty((nt, R, R, 8), dtype=torch.float32, device=dev)
+    cz = torch.empty(nt, dtype=torch.float64, device=dev)
+    st = torch.empty(nt, dtype=torch.int32, device=dev)
+    ws_recon = ls.alloc_workspace(ls.workspace_bytes(ls.OP_RECON, g, nt, ps.n), dev)
+    ws16 = ls.alloc_workspace(ls.workspace_bytes(ls.OP_REFINE, g, nt, 0, ls.BF16), dev)
+    ws32 = ls.alloc_workspace(ls.workspace_bytes(ls.OP_REFINE, g, nt, 0, ls.FP32), dev)
+    tex16 = torch.empty((nt, res, res, 4), dtype=torch.float32, device=dev)
+    tex32 = torch.empty_like(tex16)
+    log(f"workload: {nt} tiles, {ps.n} sparse points")
+
+    def step_bf16():
+        ls.recon_tiles(g, x, y, z, rgb, tl, x_out=x_out, cz_out=cz, status=st, ws=ws_recon)
+        ls.refine_tiles(w, x_out, cz, g, ls.BF16, w_bf16=wb, tex_out=tex16, want_y=False, ws=ws16)
+
+    def step_fp32():
+        ls.recon_tiles(g, x, y, z, rgb, tl, x_out=x_out, cz_out=cz, status=st, ws=ws_recon)
+        ls.refine_tiles(w, x_out, cz, g, ls.FP32, tex_out=tex32, want_y=False, ws=ws32)
+
+    # ---------------------------------------------------------------- graph
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(2):
+            step_bf16()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step_bf16()
+    torch.cuda.synchronize()
+    log("graph captured")
+    timer = Timer()
+    ms16 = timer.run(graph.replay, args.steps, args.warmup)
+    log(f"bf16 graph step {ms16:.3f} ms")
+    ms32 = timer.run(step_fp32, max(3, args.steps // 4), 2)
+    log(f"fp32 plain step {ms32:.3f} ms")
+    graph.replay()
+    torch.cuda.synchronize()
+    status = st.cpu().numpy()
+
+    # ---------------------------------------------------------------- per-kernel timing
+    reps = 3
+    ls.trace_enable(True)
+    for _ in range(reps):
+        step_bf16()
+    torch.cuda.synchronize()
+    rec = ls.trace_records()
+    ls.trace_enable(False)
+    per = {}
+    for name, ms in rec:
+        t, c = per.get(name, (0.0, 0))
+        per[name] = (t + ms, c + 1)
+    kernels = {k: {"ms_per_step": v[0] / reps, "launches_per_step": v[1] // reps} for k, v in per.items()}
+    leaf = {k: v for k, v in kernels.items() if k != "recon_all"}
+    dom = max(leaf, key=lambda k: leaf[k]["ms_per_step"])
+    flops_tile = unet_flops(res, g.pad)
+    if dom == "conv_bf16":
+        ms_dom = kernels[dom]["ms_per_step"]
+        ach = flops_tile * nt / (ms_dom * 1e-3) / 1e12
+        roof = {"kernel": "conv_bf16 (all 11 conv launches of a step)", "bound": "mfma", "achieved": ach,
+                "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_BF16_TFLOPS, "traffic": None,
+                "avg_launch_ms": ms_dom / kernels[dom]["launches_per_step"],
+                "algorithmic_per_step": f"{flops_tile * nt / 1e9:.1f} GFLOP ({flops_tile / 1e9:.4f} GFLOP/tile)"}
+    else:
+        # recon: report the output-write bytes the kernel must move (HBM floor)
+        ms_dom = kernels[dom]["ms_per_step"]
+        bytes_step = nt * R * R * 8 * 4
+        ach = bytes_step / (ms_dom * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": ach / PEAK_HBM_GBS, "traffic": None, "avg_launch_ms": ms_dom / kernels[dom]["launches_per_step"],
+                "algorithmic_per_step": f"{bytes_step / 1e6:.1f} MB written (x_out)"}
+    log(f"dominant kernel group: {dom} ({kernels[dom]['ms_per_step']:.3f} ms/step)")
+
+    out = {
+        "metric": METRIC,
+        "value": nt / (ms16 * 1e-3),
+        "unit": "tiles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms16,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "batch_1024_tiles: 32x32 tiles of 640 m, 50-2000 sparse points per tile "
+                               "(log-uniform), fBm terrain; recon + BF16 refine in one HIP graph",
+                   "tiles": nt, "sparse_points": ps.n, "res": res, "pad": g.pad, "grid": f"{R}x{R}x8"},
+        "roofline": roof,
+        "fp32_plain": {"tiles_per_s": nt / (ms32 * 1e-3), "ms_per_step": ms32},
+        "bf16_vs_fp32": ms32 / ms16,
+        "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kernels.items())},
+        "tile_status_nonzero": int((status != 0).sum()),
+    }
+
+    # ---------------------------------------------------------------- secondary figures
+    if not args.no_secondary:
+        try:
+            out["splat"] = bench_splat(args.splat_points, dev)
+        except Exception as e:  # secondary figure only
+            out["splat"] = {"error": repr(e)}
+        try:
+            out["backward"] = bench_backward(dev, w)
+        except Exception as e:
+            out["backward"] = {"error": repr(e)}
+
+    # ---------------------------------------------------------------- CPU baseline (oracle)
+    if args.cpu_tiles > 0:
+        stride = max(1, nt // args.cpu_tiles)
+        idx = np.arange(0, nt, stride)[: args.cpu_tiles]
+        log(f"oracle baseline on {len(idx)} tiles")
+        base, err = cpu_baseline(work, idx, tex16.cpu().numpy()[idx], tex32.cpu().numpy()[idx], w64)
+        out["cpu_baseline"] = base
+        out["accuracy"] = err
+    print(json.dumps(out), flush=True)
+
+
+def bench_splat(n_points: int, dev):
+    region = synth.Region(tiles_x=64, tiles_y=64)
+    g = ls.Grid.of(region)
+    ps = synth.fullres_uniform(region, n_points, seed=3, device=dev)
+    x, y, z = ps.x.contiguous(), ps.y.contiguous(), ps.z.contiguous()
+    rgb = ps.rgb_u16()
+    del ps
+    nslots = 64 * 64
+    ts = torch.arange(nslots, dtype=torch.int32, device=dev)
+    keys = torch.zeros((nslots, 64, 64), dtype=torch.int64, device=dev)
+    nd = torch.zeros(1, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    fn = lambda: ls.splat_points(g, x, y, z, rgb, ts, nslots, keys=keys, n_dropped=nd)  # noqa: E731
+    fn()
+    torch.cuda.synchronize()
+    ls.trace_enable(True)
+    reps = 5
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    ms = sum(t for n, t in ls.trace_records() if n == "splat") / reps
+    ls.trace_enable(False)
+    alg_bytes = n_points * 18 + nslots * 64 * 64 * 8
+    return {"workload": f"{n_points} points, 64x64 tiles, Morton-ordered", "ms": ms,
+            "points_per_s": n_points / (ms * 1e-3), "algorithmic_GBps": alg_bytes / (ms * 1e-3) / 1e9,
+            "frac_hbm_peak": alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+
+
+def bench_backward(dev, w):
+    work = synth.train_tiles(seed=4, device=dev)
+    g = ls.Grid.of(work.region)
+    ps = work.points
+    tl = torch.from_numpy(work.tile_list).to(dev)
+    xo, cz, _ = ls.recon_tiles(g, ps.x, ps.y, ps.z, ps.rgb_u16(), tl)
+    nt = xo.shape[0]
+    gy = torch.randn((nt, 64, 64, 4), device=dev, generator=torch.Generator(device=dev).manual_seed(0))
+    act = torch.empty(ls.act_bytes(g, nt, ls.FP32), dtype=torch.uint8, device=dev)
+    ws = ls.alloc_workspace(ls.workspace_bytes(ls.OP_BACKWARD, g, nt, 0, ls.FP32), dev)
+    gw = torch.empty_like(w)
+
+    def step():
+        ls.refine_tiles(w, xo, cz, g, ls.FP32, act_save=act, want_y=True, want_tex=False, ws=ws)
+        ls.refine_backward(w, xo, gy, g, ls.FP32, act_save=act, grad_w=gw, ws=ws)
+    ms = Timer().run(step, 3, 1)
+    return {"workload": f"{nt} tiles, FP32 forward + backward", "ms_per_step": ms, "tiles_per_s": nt / (ms * 1e-3)}
+
+
+if __name__ == "__main__":
+    main()

@@ -172,6 +172,16 @@ int ls_conv_num_configs(int layer, int precision, int pass);
 int ls_set_conv_config(int layer, int precision, int pass, int config);
 int ls_get_conv_config(int layer, int precision, int pass);
 
+/* Launch timing for measurement (not part of the method).  When enabled,
+ * every kernel group the library enqueues is bracketed by a pair of HIP
+ * events recorded on its stream (up to 16384 groups; the count restarts at
+ * each ls_trace_enable call).  ls_trace_record(i) waits for group i and
+ * returns its kernel-group name (static host string) and elapsed ms.  Leave
+ * disabled (the default) when capturing HIP graphs. */
+int ls_trace_enable(int on);
+int ls_trace_count(void);
+int ls_trace_record(int i, const char** name, float* ms);
+
 const char* ls_status_string(int status);
 /* Text of the last LS_EHIP error on this thread (host string). */
 const char* ls_last_error(void);

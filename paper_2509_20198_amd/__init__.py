@@ -29,7 +29,7 @@ EXPORTS = [
     "ls_num_params", "ls_workspace_bytes", "ls_act_bytes", "ls_recon_tiles", "ls_refine_tiles",
     "ls_refine_backward", "ls_splat_points", "ls_resolve_keys", "ls_pack_weights_bf16",
     "ls_conv_num_configs", "ls_set_conv_config", "ls_get_conv_config", "ls_status_string",
-    "ls_last_error", "ls_version",
+    "ls_last_error", "ls_version", "ls_trace_enable", "ls_trace_count", "ls_trace_record",
 ]
 
 
@@ -114,6 +114,11 @@ def load_library(path: str = LIB_PATH):
         lib.ls_status_string.argtypes = [ctypes.c_int]
         lib.ls_last_error.restype = ctypes.c_char_p
         lib.ls_version.restype = ctypes.c_char_p
+        lib.ls_trace_enable.restype = ctypes.c_int
+        lib.ls_trace_enable.argtypes = [ctypes.c_int]
+        lib.ls_trace_count.restype = ctypes.c_int
+        lib.ls_trace_record.restype = ctypes.c_int
+        lib.ls_trace_record.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float)]
         _lib = lib
         return lib
 
@@ -350,3 +355,20 @@ def get_conv_config(layer: int, precision: int, pass_: int) -> int:
 
 def conv_num_configs(layer: int, precision: int, pass_: int) -> int:
     return int(load_library().ls_conv_num_configs(layer, precision, pass_))
+
+
+def trace_enable(on: bool = True):
+    """Bracket every kernel group the library enqueues with HIP events."""
+    _check(load_library().ls_trace_enable(1 if on else 0), "ls_trace_enable")
+
+
+def trace_records():
+    """[(kernel group name, elapsed ms)] for the groups recorded since trace_enable."""
+    lib = load_library()
+    out = []
+    for i in range(lib.ls_trace_count()):
+        name = ctypes.c_char_p()
+        ms = ctypes.c_float()
+        _check(lib.ls_trace_record(i, ctypes.byref(name), ctypes.byref(ms)), "ls_trace_record")
+        out.append((name.value.decode(), float(ms.value)))
+    return out

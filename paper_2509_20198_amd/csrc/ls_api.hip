@@ -28,7 +28,25 @@ void cfg_init() {
   g_conv_cfg_init = true;
 }
 
+constexpr int TRACE_MAX = 16384;
+bool g_trace_on = false;
+bool g_trace_init = false;
+int g_trace_n = 0;
+hipEvent_t g_trace_ev[2 * TRACE_MAX];
+const char* g_trace_name[TRACE_MAX];
+
 }  // namespace
+
+LsTrace::LsTrace(const char* name, hipStream_t s) : slot(-1), st(s) {
+  if (!g_trace_on || g_trace_n >= TRACE_MAX) return;
+  slot = g_trace_n++;
+  g_trace_name[slot] = name;
+  (void)hipEventRecord(g_trace_ev[2 * slot], st);
+}
+
+LsTrace::~LsTrace() {
+  if (slot >= 0) (void)hipEventRecord(g_trace_ev[2 * slot + 1], st);
+}
 
 void ls_set_last_error(hipError_t e, const char* what, int line) {
   snprintf(g_last_error, sizeof(g_last_error), "%s (%d) at %s, line %d", hipGetErrorString(e), (int)e, what, line);
@@ -44,6 +62,8 @@ int ls_zero_f32(float* p, int64_t n, hipStream_t st) {
 
 int ls_conv_num_configs_impl(int layer, int precision, int pass) {
   if (layer < 0 || layer >= LS_NLAYER || precision < 0 || precision > 1 || pass < 0 || pass > 2) return 0;
+  // BF16 forward: 0 = direct global-memory operand fetch, 1 = LDS-staged 16x16 tile
+  if (precision == LS_BF16 && pass == 0) return 2;
   return 1;
 }
 int ls_conv_config_get(int layer, int precision, int pass) {
@@ -166,6 +186,26 @@ int ls_resolve_keys(const ls_grid* g, const uint64_t* keys, int32_t n_slots, flo
 int ls_pack_weights_bf16(const float* w, uint16_t* w_bf16, void* stream) {
   if (!w || !w_bf16) return LS_EINVAL;
   return ls_pack_bf16(w, w_bf16, LS_NUM_PARAMS, ls_stream(stream));
+}
+
+int ls_trace_enable(int on) {
+  if (on && !g_trace_init) {
+    for (int i = 0; i < 2 * TRACE_MAX; ++i) LS_HOST_CHECK(hipEventCreate(&g_trace_ev[i]));
+    g_trace_init = true;
+  }
+  g_trace_on = on != 0;
+  g_trace_n = 0;
+  return LS_OK;
+}
+
+int ls_trace_count(void) { return g_trace_n; }
+
+int ls_trace_record(int i, const char** name, float* ms) {
+  if (i < 0 || i >= g_trace_n || !name || !ms) return LS_EINVAL;
+  LS_HOST_CHECK(hipEventSynchronize(g_trace_ev[2 * i + 1]));
+  LS_HOST_CHECK(hipEventElapsedTime(ms, g_trace_ev[2 * i], g_trace_ev[2 * i + 1]));
+  *name = g_trace_name[i];
+  return LS_OK;
 }
 
 int ls_conv_num_configs(int layer, int precision, int pass) { return ls_conv_num_configs_impl(layer, precision, pass); }

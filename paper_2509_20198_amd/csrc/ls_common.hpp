@@ -26,6 +26,19 @@
 
 void ls_set_last_error(hipError_t e, const char* what, int line);
 
+// Optional launch timing: when enabled with ls_trace_enable(), a scope
+// records a start event on `st` at construction and a stop event at the end
+// of the scope, so the pair brackets the kernels the scope enqueues.
+struct LsTrace {
+  LsTrace(const char* name, hipStream_t st);
+  ~LsTrace();
+  int slot;
+  hipStream_t st;
+};
+#define LS_TRACE_CAT2(a, b) a##b
+#define LS_TRACE_CAT(a, b) LS_TRACE_CAT2(a, b)
+#define LS_TRACE(name, st) LsTrace LS_TRACE_CAT(ls_trace_, __LINE__)(name, st)
+
 static inline hipStream_t ls_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 static inline size_t ls_align(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }

@@ -34,9 +34,11 @@
 
 namespace {
 
-constexpr int RB = 256;                  // threads per recon workgroup
+constexpr int RB = 512;                  // threads per recon workgroup
+constexpr int LDS_INTS = 19456;          // 76 KB of LDS per recon workgroup (two per CU)
 constexpr int MAXG = 90;                 // max buckets per side
 constexpr int MAXB = MAXG * MAXG;        // max buckets
+static_assert(2 * (MAXB + 1) <= LDS_INTS, "bucket offsets must fit twice in the recon LDS");
 constexpr int STAR_MAX_STEPS = 1024;     // safeguard on one point's star walk
 constexpr uint64_t FACE_NONE = ~0ull;
 constexpr int SORT_LDS = 16384;          // bin segments up to this size sort in LDS
@@ -205,7 +207,8 @@ struct ReconParams {
   const int32_t* bin_off;
   const int32_t* bin_idx;
   const int32_t* flags;
-  // per bin entry scratch: staging (reused for the canonical points) and sorted
+  // per bin entry scratch: staging (reused for the canonical heights and
+  // colours), sorted copies, canonical coordinates
   int32_t* su;
   int32_t* sv;
   int32_t* sz;
@@ -215,6 +218,7 @@ struct ReconParams {
   int32_t* tv;
   int32_t* tz;
   uint64_t* trgb;
+  int2* cuv;
   // per workgroup scratch
   uint64_t* facemap;  // [gridDim][R*R]
   int32_t* nnidx;     // [gridDim][R*R]
@@ -225,9 +229,8 @@ struct ReconParams {
 };
 
 struct Tile {
-  const int32_t* u;
-  const int32_t* v;
-  const int32_t* boff;  // LDS, G*G + 1
+  const int2* uv;       // canonical coordinates (LDS when the tile fits, else global)
+  const int32_t* boff;  // LDS, G*G + 1 canonical bucket offsets
   int G, H, W2;
   double bw;  // bucket width in raw units
 };
@@ -244,11 +247,10 @@ __device__ __forceinline__ int sgn_d(double v) { return (v > 0.0) - (v < 0.0); }
 // Sign of the in-circle determinant of d against CCW (a, b, c): > 0 when d
 // is strictly inside.  Floating-point filter first, exact int128 otherwise,
 // then the symbolic perturbation for exactly cocircular points.
-__device__ int incircle_sos(const Tile& T, int a, int b, int c, int d) {
-  const int64_t ux = T.u[d], uy = T.v[d];
-  const int64_t adx = T.u[a] - ux, ady = T.v[a] - uy;
-  const int64_t bdx = T.u[b] - ux, bdy = T.v[b] - uy;
-  const int64_t cdx = T.u[c] - ux, cdy = T.v[c] - uy;
+__device__ int incircle_sos(const Tile& T, int a, int b, int c, int d, int2 pa, int2 pb, int2 pc, int2 pd) {
+  const int64_t adx = pa.x - pd.x, ady = pa.y - pd.y;
+  const int64_t bdx = pb.x - pd.x, bdy = pb.y - pd.y;
+  const int64_t cdx = pc.x - pd.x, cdy = pc.y - pd.y;
   const double fadx = (double)adx, fady = (double)ady, fbdx = (double)bdx, fbdy = (double)bdy;
   const double fcdx = (double)cdx, fcdy = (double)cdy;
   const double al = fadx * fadx + fady * fady;
@@ -271,18 +273,15 @@ __device__ int incircle_sos(const Tile& T, int a, int b, int c, int d) {
   if (c < w) w = c;
   if (d < w) w = d;
   if (w == d) return -1;
-  auto o = [&](int p, int q, int r) {
-    return sgn_d(orient_d(T.u[p], T.v[p], T.u[q], T.v[q], T.u[r], T.v[r]));
-  };
-  if (w == a) return o(b, c, d);
-  if (w == b) return o(c, a, d);
-  return o(a, b, d);
+  if (w == a) return sgn_d(orient_d(pb.x, pb.y, pc.x, pc.y, pd.x, pd.y));
+  if (w == b) return sgn_d(orient_d(pc.x, pc.y, pa.x, pa.y, pd.x, pd.y));
+  return sgn_d(orient_d(pa.x, pa.y, pb.x, pb.y, pd.x, pd.y));
 }
 
-// Visit the buckets at Chebyshev ring r around (bx0, by0); returns false if
-// the ring lies completely outside the grid.
-template <class F>
-__device__ __forceinline__ void ring_visit(const Tile& T, int bx0, int by0, int r, F&& f) {
+// Visit the buckets at Chebyshev ring r around (bx0, by0) that `keep`
+// accepts, then every point of those buckets.
+template <class K, class F>
+__device__ __forceinline__ void ring_visit(const Tile& T, int bx0, int by0, int r, K&& keep, F&& f) {
   const int G = T.G;
   const int ylo = by0 - r, yhi = by0 + r, xlo = bx0 - r, xhi = bx0 + r;
   for (int by = ylo < 0 ? 0 : ylo; by <= (yhi < G ? yhi : G - 1); ++by) {
@@ -290,8 +289,10 @@ __device__ __forceinline__ void ring_visit(const Tile& T, int bx0, int by0, int 
     const int step = full ? 1 : (xhi - xlo);
     for (int bx = xlo; bx <= xhi; bx += (step > 0 ? step : 1)) {
       if (bx < 0 || bx >= G) continue;
+      if (!keep(bx, by)) continue;
       const int b = by * G + bx;
-      for (int p = T.boff[b]; p < T.boff[b + 1]; ++p) f(p);
+      const int e = T.boff[b + 1];
+      for (int p = T.boff[b]; p < e; ++p) f(p);
     }
   }
 }
@@ -307,17 +308,18 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
   int best = -1;
   int64_t bd = 0;
   int bu = 0, bv = 0;
+  auto all = [](int, int) { return true; };
   for (int r = 0;; ++r) {
-    ring_visit(T, bx0, by0, r, [&](int p) {
+    ring_visit(T, bx0, by0, r, all, [&](int p) {
       if (p == skip) return;
-      const int pu = T.u[p], pv = T.v[p];
-      const int64_t dx = pu - qx, dy = pv - qy;
+      const int2 q = T.uv[p];
+      const int64_t dx = q.x - qx, dy = q.y - qy;
       const int64_t d = dx * dx + dy * dy;
-      if (best < 0 || d < bd || (d == bd && (pv < bv || (pv == bv && pu < bu)))) {
+      if (best < 0 || d < bd || (d == bd && (q.y < bv || (q.y == bv && q.x < bu)))) {
         best = p;
         bd = d;
-        bu = pu;
-        bv = pv;
+        bu = q.x;
+        bv = q.y;
       }
     });
     if (best >= 0) {
@@ -332,27 +334,48 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
 // The third vertex of the Delaunay triangle on the left of edge a->b: the
 // first point met by a circle through a and b whose centre moves left.
 // Returns -1 if no point lies strictly left of a->b (a->b is a hull edge).
+// Buckets entirely on the right of the line, or (once a candidate exists)
+// entirely outside its circumcircle, are skipped.
 __device__ int third_left(const Tile& T, int a, int b) {
-  const int ax = T.u[a], ay = T.v[a], bx = T.u[b], by = T.v[b];
+  const int2 A = T.uv[a], B = T.uv[b];
+  const int ax = A.x, ay = A.y, bx = B.x, by = B.y;
   const int mx = (ax + bx) >> 1, my = (ay + by) >> 1;
   const int bx0 = bucket_1d(mx + T.H, T.G, T.W2), by0 = bucket_1d(my + T.H, T.G, T.W2);
   int best = -1;
-  double stop = 0.0;
+  int2 C = make_int2(0, 0);
+  double stop = 0.0, ocx = 0.0, ocy = 0.0, rho = 0.0;  // circle centre (tile-local) and radius
   const double fbx = bx - ax, fby = by - ay;
   const double bl = fbx * fbx + fby * fby;
+  auto keep = [&](int qx, int qy) {
+    // bucket rectangle in tile-local coordinates, rounded outwards to integers
+    const double x0 = floor(qx * T.bw) - T.H - 1.0, x1 = ceil((qx + 1) * T.bw) - T.H + 1.0;
+    const double y0 = floor(qy * T.bw) - T.H - 1.0, y1 = ceil((qy + 1) * T.bw) - T.H + 1.0;
+    const double o00 = orient_d(ax, ay, bx, by, x0, y0), o10 = orient_d(ax, ay, bx, by, x1, y0);
+    const double o01 = orient_d(ax, ay, bx, by, x0, y1), o11 = orient_d(ax, ay, bx, by, x1, y1);
+    if (fmax(fmax(o00, o10), fmax(o01, o11)) <= 0.0) return false;
+    if (best >= 0) {
+      const double dx = fmax(fmax(x0 - ocx, ocx - x1), 0.0), dy = fmax(fmax(y0 - ocy, ocy - y1), 0.0);
+      const double lim = rho * (1.0 + 1e-9) + 2.0;
+      if (dx * dx + dy * dy > lim * lim) return false;
+    }
+    return true;
+  };
   for (int r = 0;; ++r) {
-    ring_visit(T, bx0, by0, r, [&](int p) {
+    ring_visit(T, bx0, by0, r, keep, [&](int p) {
       if (p == a || p == b) return;
-      const double px = T.u[p], py = T.v[p];
-      if (orient_d(ax, ay, bx, by, px, py) <= 0.0) return;
-      if (best < 0 || incircle_sos(T, a, b, best, p) > 0) {
+      const int2 P = T.uv[p];
+      if (orient_d(ax, ay, bx, by, P.x, P.y) <= 0.0) return;
+      if (best < 0 || incircle_sos(T, a, b, best, p, A, B, C, P) > 0) {
         best = p;
+        C = P;
         // circumcircle of (a, b, p) relative to a, and its reach from the midpoint
-        const double cx = px - ax, cy = py - ay;
+        const double cx = P.x - ax, cy = P.y - ay;
         const double cl = cx * cx + cy * cy;
         const double D = 2.0 * (fbx * cy - fby * cx);
         const double ox = (cy * bl - fby * cl) / D, oy = (fbx * cl - cx * bl) / D;
-        const double rho = sqrt(ox * ox + oy * oy);
+        rho = sqrt(ox * ox + oy * oy);
+        ocx = ox + ax;
+        ocy = oy + ay;
         const double dmx = ox - (mx - ax), dmy = oy - (my - ay);
         stop = (sqrt(dmx * dmx + dmy * dmy) + rho) * (1.0 + 1e-9) + 2.0;
       }
@@ -402,7 +425,8 @@ __device__ __forceinline__ void texel_range(int lo, int hi, int H, int C, int R,
 }
 
 __device__ void raster_triangle(const Tile& T, int a, int b, int c, int C, int R, uint64_t* __restrict__ fm) {
-  const int ax = T.u[a], ay = T.v[a], bx = T.u[b], by = T.v[b], cx = T.u[c], cy = T.v[c];
+  const int2 A = T.uv[a], B = T.uv[b], Cc = T.uv[c];
+  const int ax = A.x, ay = A.y, bx = B.x, by = B.y, cx = Cc.x, cy = Cc.y;
   int i0, i1, j0, j1;
   texel_range(min(ax, min(bx, cx)), max(ax, max(bx, cx)), T.H, C, R, j0, j1);
   texel_range(min(ay, min(by, cy)), max(ay, max(by, cy)), T.H, C, R, i0, i1);
@@ -426,7 +450,8 @@ __device__ void raster_triangle(const Tile& T, int a, int b, int c, int C, int R
 
 // Texels lying exactly on hull edge a->b get the triangle next to it.
 __device__ void raster_hull_edge(const Tile& T, int a, int b, uint64_t key, int C, int R, uint64_t* __restrict__ fm) {
-  const int ax = T.u[a], ay = T.v[a], bx = T.u[b], by = T.v[b];
+  const int2 A = T.uv[a], B = T.uv[b];
+  const int ax = A.x, ay = A.y, bx = B.x, by = B.y;
   int i0, i1, j0, j1;
   texel_range(min(ax, bx), max(ax, bx), T.H, C, R, j0, j1);
   texel_range(min(ay, by), max(ay, by), T.H, C, R, i0, i1);
@@ -488,8 +513,9 @@ __device__ __forceinline__ void write_zero_tile(const ReconParams& P, int k) {
 }
 
 __global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
-  __shared__ int s_b[MAXB + 1];  // bucket counts -> offsets (raw)
-  __shared__ int s_k[MAXB + 1];  // kept counts -> canonical bucket offsets
+  // region 0 holds the raw bucket offsets while bucketing, then the
+  // canonical coordinates; the canonical bucket offsets sit at the end
+  __shared__ int s_mem[LDS_INTS];
   __shared__ int s_tmp[RB / 64 + 1];
   __shared__ int s_tile;
   __shared__ int s_flags;
@@ -529,6 +555,9 @@ __global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
       G = want < 1 ? 1 : (want > MAXG ? MAXG : want);
     }
     const int NB = G * G;
+    int* s_b = s_mem;
+    int* s_k = s_mem + LDS_INTS - (NB + 1);
+    const bool uv_lds = 2 * cnt <= LDS_INTS - (NB + 1);
     // ---- a. gather + bucket histogram
     for (int b = tid; b <= NB; b += RB) s_b[b] = 0;
     if (tid == 0) s_flags = 0;
@@ -588,17 +617,19 @@ __global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
       int w = off + s_k[b];
       for (int i = lo; i < hi; ++i)
         if (i == lo || P.tu[i] != P.tu[i - 1] || P.tv[i] != P.tv[i - 1]) {
-          P.su[w] = P.tu[i];
-          P.sv[w] = P.tv[i];
+          P.cuv[w] = make_int2(P.tu[i], P.tv[i]);
           P.sz[w] = P.tz[i];
           P.srgb[w] = P.trgb[i];
           ++w;
         }
     }
     __syncthreads();
+    int2* s_uv = reinterpret_cast<int2*>(s_mem);
+    if (uv_lds)
+      for (int p = tid; p < m; p += RB) s_uv[p] = P.cuv[off + p];
+    __syncthreads();
     Tile T;
-    T.u = P.su + off;
-    T.v = P.sv + off;
+    T.uv = uv_lds ? s_uv : P.cuv + off;
     T.boff = s_k;
     T.G = G;
     T.H = H;
@@ -615,20 +646,24 @@ __global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
     }
     // collinearity check
     bool noncol = false;
-    if (m >= 3)
-      for (int p = tid; p < m; p += RB)
-        if (orient_d(T.u[0], T.v[0], T.u[1], T.v[1], T.u[p], T.v[p]) != 0.0) noncol = true;
+    if (m >= 3) {
+      const int2 p0 = T.uv[0], p1 = T.uv[1];
+      for (int p = tid; p < m; p += RB) {
+        const int2 q = T.uv[p];
+        if (orient_d(p0.x, p0.y, p1.x, p1.y, q.x, q.y) != 0.0) noncol = true;
+      }
+    }
     // face keys pack three point indices in 21 bits each
     const bool has_dt = (__syncthreads_or(noncol) != 0) && m < (1 << 21);
     if (m >= (1 << 21) && tid == 0) atomicOr(&s_flags, LS_TILE_DEGENERATE);
     // ---- d. Delaunay stars, rasterised into the face map
     if (has_dt) {
       for (int a = tid; a < m; a += RB) {
-        const int b0 = ring_nearest(T, T.u[a], T.v[a], a);
+        const int b0 = ring_nearest(T, T.uv[a].x, T.uv[a].y, a);
         int b = b0;
         bool closed = false;
         int steps = 0;
-        int prev_b = -1;      // second vertex of the last CCW triangle
+        int prev_b = -1;  // second vertex of the last CCW triangle
         uint64_t hull_key = FACE_NONE;
         int hull_b = -1;
         while (steps++ < STAR_MAX_STEPS) {
@@ -674,13 +709,14 @@ __global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
         out4[1] = (double)(c & 0xFFFF);
         out4[2] = (double)((c >> 16) & 0xFFFF);
         out4[3] = (double)((c >> 32) & 0xFFFF);
-        return false;
+        return;
       }
       const int a = (int)(f >> 42), b = (int)((f >> 21) & 0x1FFFFF), c = (int)(f & 0x1FFFFF);
+      const int2 A = T.uv[a], B = T.uv[b], Cc = T.uv[c];
       const double qx = q0 + j * C, qy = q0 + i * C;
-      const double ob = orient_d(T.u[c], T.v[c], T.u[a], T.v[a], qx, qy);
-      const double oc = orient_d(T.u[a], T.v[a], T.u[b], T.v[b], qx, qy);
-      const double O = orient_d(T.u[a], T.v[a], T.u[b], T.v[b], T.u[c], T.v[c]);
+      const double ob = orient_d(Cc.x, Cc.y, A.x, A.y, qx, qy);
+      const double oc = orient_d(A.x, A.y, B.x, B.y, qx, qy);
+      const double O = orient_d(A.x, A.y, B.x, B.y, Cc.x, Cc.y);
       const double lb = ob / O, lc = oc / O;
       const double za = Tz[a], zb = Tz[b], zc = Tz[c];
       const double h = za + lb * (zb - za) + lc * (zc - za);
@@ -691,7 +727,6 @@ __global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
                      vc = (double)((cc >> (16 * ch)) & 0xFFFF);
         out4[1 + ch] = va + lb * (vb - va) + lc * (vc - va);
       }
-      return true;
     };
     if (tid == 0) {
       double v4[4];
@@ -748,6 +783,7 @@ struct ReconLayout {
   int32_t* sort_scratch;
   int32_t *su, *sv, *sz, *sslot, *tu, *tv, *tz;
   uint64_t *srgb, *trgb;
+  int2* cuv;
   uint64_t* facemap;
   int32_t* nnidx;
   int n_wg;
@@ -787,6 +823,7 @@ size_t recon_layout(const LsGridInfo& gi, int32_t n_tiles, int64_t n, void* base
   L->tz = A.take<int32_t>(E);
   L->srgb = A.take<uint64_t>(E);
   L->trgb = A.take<uint64_t>(E);
+  L->cuv = A.take<int2>(E);
   L->facemap = A.take<uint64_t>(RR * nwg);
   L->nnidx = A.take<int32_t>(RR * nwg);
   L->n_wg = nwg;
@@ -817,6 +854,7 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   const int64_t nall = (int64_t)gi.tx * gi.ty;
 
   const int T = 256;
+  LS_TRACE("recon_all", st);
   auto blocks = [&](int64_t cnt) { return (int)std::min<int64_t>((cnt + T - 1) / T, 65535); };
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks(nall)), dim3(T), 0, st, L.tile_pos, nall, 0x7fffffff);
   hipLaunchKernelGGL(k_fill_i32, dim3(blocks(n_tiles + 1)), dim3(T), 0, st, L.counts, (int64_t)n_tiles + 1, 0);
@@ -850,9 +888,18 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   bp.cap = cap;
   bp.flags = L.flags;
   const int pb = (int)std::min<int64_t>((n + T - 1) / T, 8192);
-  if (n > 0) hipLaunchKernelGGL(k_bin_count, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, bp);
-  if (n > 0) hipLaunchKernelGGL(k_bin_scatter, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
+  {
+    LS_TRACE("bin_count", st);
+    if (n > 0) hipLaunchKernelGGL(k_bin_count, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
+  }
+  {
+    LS_TRACE("bin_scan", st);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, bp);
+  }
+  {
+    LS_TRACE("bin_scatter", st);
+    if (n > 0) hipLaunchKernelGGL(k_bin_scatter, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
+  }
   if (user_csr)
     hipLaunchKernelGGL(k_bin_sort, dim3(std::min(n_tiles, 4 * num_cus())), dim3(RB), 0, st, boff, n_tiles, bidx,
                        L.sort_scratch, L.flags);
@@ -887,13 +934,17 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   rp.tv = L.tv;
   rp.tz = L.tz;
   rp.trgb = L.trgb;
+  rp.cuv = L.cuv;
   rp.facemap = L.facemap;
   rp.nnidx = L.nnidx;
   rp.queue = L.queue;
   rp.x_out = x_out;
   rp.cz_out = cz_out;
   rp.status = tile_status;
-  hipLaunchKernelGGL(k_recon, dim3(L.n_wg), dim3(RB), 0, st, rp);
+  {
+    LS_TRACE("recon_tile", st);
+    hipLaunchKernelGGL(k_recon, dim3(L.n_wg), dim3(RB), 0, st, rp);
+  }
   LS_LAUNCH_CHECK();
   return LS_OK;
 }

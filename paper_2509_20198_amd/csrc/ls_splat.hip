@@ -19,16 +19,19 @@
 namespace {
 
 constexpr int SPLAT_THREADS = 256;
-constexpr int SPLAT_PPT = 16;
-constexpr int SPLAT_BATCH = SPLAT_THREADS * SPLAT_PPT;  // points per batch
-constexpr int SPLAT_WIN = 8192;                         // LDS window (64 KB of keys)
+constexpr int SPLAT_PAIRS = 8;                                   // point pairs per thread per batch
+constexpr int SPLAT_PPT = 2 * SPLAT_PAIRS;                       // points per thread per batch
+constexpr int SPLAT_BATCH = SPLAT_THREADS * SPLAT_PPT;           // points per batch
+constexpr int SPLAT_WIN = 8192;                                  // LDS window (64 KB of keys)
 
 struct SplatParams {
   int64_t ox, oy;
   int32_t C, res, tiles_x, tiles_y;
+  double inv_C, inv_res;
   int32_t gw, gh;  // global texel extent
   int32_t n_slots;
   int32_t morton_ok;
+  int32_t vec_ok;  // x, y, z 8-byte aligned and rgb 4-byte aligned: pairwise vector loads
   int64_t n;
   const int32_t* x;
   const int32_t* y;
@@ -57,71 +60,121 @@ __device__ __forceinline__ uint32_t compact16(uint32_t v) {
   return v;
 }
 
-__device__ __forceinline__ int64_t fdiv(int64_t a, int64_t b) {
-  int64_t q = a / b;
-  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+// floor(a / b) for 0 <= a < 2^31, b > 0, from a double reciprocal plus a
+// one-step correction (the product is within one of the quotient)
+__device__ __forceinline__ int udiv(int64_t a, int b, double inv) {
+  int q = (int)((double)a * inv);
+  if ((int64_t)q * b > a) --q;
+  else if ((int64_t)(q + 1) * b <= a) ++q;
   return q;
 }
 
-// texel index of (gx, gy) in the key array, or -1 if its tile is unmapped
+// texel index of (gx, gy) in the key array; the tile must be mapped
 __device__ __forceinline__ int64_t cell_of(const SplatParams& p, int gx, int gy) {
-  const int tx = gx / p.res, ty = gy / p.res;
+  const int tx = udiv(gx, p.res, p.inv_res), ty = udiv(gy, p.res, p.inv_res);
   const int s = p.tile_slot[ty * p.tiles_x + tx];
-  if (s < 0 || s >= p.n_slots) return -1;
   return ((int64_t)s * p.res + (gy - ty * p.res)) * p.res + (gx - tx * p.res);
+}
+
+// Key and texel of one point; returns false (dropped) outside the region or
+// in an unmapped tile.
+__device__ __forceinline__ bool point_key(const SplatParams& p, int xi, int yi, int zi, uint32_t r, uint32_t g,
+                                          uint32_t b, unsigned long long& key, int& gx, int& gy) {
+  const int64_t dx = (int64_t)xi - p.ox, dy = (int64_t)yi - p.oy;
+  if (dx < 0 || dy < 0) return false;
+  if (dx >= (int64_t)p.gw * p.C || dy >= (int64_t)p.gh * p.C) return false;
+  gx = udiv(dx, p.C, p.inv_C);
+  gy = udiv(dy, p.C, p.inv_C);
+  const int tx = udiv(gx, p.res, p.inv_res), ty = udiv(gy, p.res, p.inv_res);
+  const int32_t s = p.tile_slot[ty * p.tiles_x + tx];
+  if (s < 0 || s >= p.n_slots) return false;
+  const uint32_t zz = (uint32_t)zi ^ 0x80000000u;
+  key = ((unsigned long long)zz << 32) | ((unsigned long long)(r >> 8) << 24) | ((unsigned long long)(g >> 8) << 16) |
+        ((unsigned long long)(b >> 8) << 8) | 0xFFull;
+  return true;
 }
 
 __global__ void __launch_bounds__(SPLAT_THREADS) k_splat(SplatParams p) {
   __shared__ unsigned long long s_win[SPLAT_WIN];
-  __shared__ uint32_t s_lo, s_hi;
-  __shared__ unsigned long long s_drop;
-  const int tid = threadIdx.x;
+  __shared__ uint32_t s_lo[SPLAT_THREADS / 64], s_hi[SPLAT_THREADS / 64];
+  __shared__ unsigned long long s_drop[SPLAT_THREADS / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   unsigned long long dropped = 0;
   for (int64_t base = (int64_t)blockIdx.x * SPLAT_BATCH; base < p.n; base += (int64_t)gridDim.x * SPLAT_BATCH) {
-    uint32_t mc[SPLAT_PPT];
     unsigned long long key[SPLAT_PPT];
     int gxs[SPLAT_PPT], gys[SPLAT_PPT];
     uint32_t lo = 0xFFFFFFFFu, hi = 0;
+    const int64_t pbase = base >> 1;
 #pragma unroll
-    for (int k = 0; k < SPLAT_PPT; ++k) {
-      const int64_t i = base + (int64_t)k * SPLAT_THREADS + tid;
-      key[k] = 0;
-      gxs[k] = -1;
-      gys[k] = -1;
-      if (i >= p.n) continue;
-      const int64_t gx = fdiv((int64_t)p.x[i] - p.ox, p.C), gy = fdiv((int64_t)p.y[i] - p.oy, p.C);
-      if (gx < 0 || gy < 0 || gx >= p.gw || gy >= p.gh) {
-        ++dropped;
-        continue;
+    for (int k = 0; k < SPLAT_PAIRS; ++k) {
+      const int64_t pr = pbase + (int64_t)k * SPLAT_THREADS + tid;
+      const int64_t i0 = 2 * pr;
+      int xv[2], yv[2], zv[2];
+      uint32_t rv[2], gv[2], bv[2];
+      int nv = 0;
+      if (p.vec_ok && i0 + 1 < p.n) {
+        const int2 x2 = reinterpret_cast<const int2*>(p.x)[pr];
+        const int2 y2 = reinterpret_cast<const int2*>(p.y)[pr];
+        const int2 z2 = reinterpret_cast<const int2*>(p.z)[pr];
+        const uint32_t* c = reinterpret_cast<const uint32_t*>(p.rgb) + 3 * pr;
+        const uint32_t c0 = c[0], c1 = c[1], c2 = c[2];
+        xv[0] = x2.x; xv[1] = x2.y;
+        yv[0] = y2.x; yv[1] = y2.y;
+        zv[0] = z2.x; zv[1] = z2.y;
+        rv[0] = c0 & 0xFFFF; gv[0] = c0 >> 16; bv[0] = c1 & 0xFFFF;
+        rv[1] = c1 >> 16; gv[1] = c2 & 0xFFFF; bv[1] = c2 >> 16;
+        nv = 2;
+      } else {
+        for (int q = 0; q < 2; ++q) {
+          const int64_t i = i0 + q;
+          if (i >= p.n) break;
+          xv[q] = p.x[i];
+          yv[q] = p.y[i];
+          zv[q] = p.z[i];
+          rv[q] = p.rgb[3 * i];
+          gv[q] = p.rgb[3 * i + 1];
+          bv[q] = p.rgb[3 * i + 2];
+          nv = q + 1;
+        }
       }
-      const int32_t slot = p.tile_slot[(gy / p.res) * p.tiles_x + gx / p.res];
-      if (slot < 0 || slot >= p.n_slots) {
-        ++dropped;
-        continue;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int slot = 2 * k + q;
+        key[slot] = 0;
+        if (q >= nv) continue;
+        int gx, gy;
+        if (!point_key(p, xv[q], yv[q], zv[q], rv[q], gv[q], bv[q], key[slot], gx, gy)) {
+          key[slot] = 0;
+          ++dropped;
+          continue;
+        }
+        gxs[slot] = gx;
+        gys[slot] = gy;
+        if (p.morton_ok) {
+          const uint32_t mc = spread16((uint32_t)gx) | (spread16((uint32_t)gy) << 1);
+          lo = min(lo, mc);
+          hi = max(hi, mc);
+        }
       }
-      const uint16_t* c = p.rgb + 3 * i;
-      const uint32_t zz = (uint32_t)p.z[i] ^ 0x80000000u;
-      key[k] = ((unsigned long long)zz << 32) | ((unsigned long long)(c[0] >> 8) << 24) |
-               ((unsigned long long)(c[1] >> 8) << 16) | ((unsigned long long)(c[2] >> 8) << 8) | 0xFFull;
-      gxs[k] = (int)gx;
-      gys[k] = (int)gy;
-      mc[k] = spread16((uint32_t)gx) | (spread16((uint32_t)gy) << 1);
-      lo = min(lo, mc[k]);
-      hi = max(hi, mc[k]);
     }
     bool use_lds = false;
     if (p.morton_ok) {
-      if (tid == 0) {
-        s_lo = 0xFFFFFFFFu;
-        s_hi = 0;
+      // block min / max of the Morton codes: wave shuffles, then 4 values
+      for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+      }
+      if (lane == 0) {
+        s_lo[wave] = lo;
+        s_hi[wave] = hi;
       }
       __syncthreads();
-      if (hi >= lo) {
-        atomicMin(&s_lo, lo);
-        atomicMax(&s_hi, hi);
+      uint32_t blo = s_lo[0], bhi = s_hi[0];
+#pragma unroll
+      for (int w = 1; w < SPLAT_THREADS / 64; ++w) {
+        blo = min(blo, s_lo[w]);
+        bhi = max(bhi, s_hi[w]);
       }
-      __syncthreads();
-      const uint32_t blo = s_lo, bhi = s_hi;
       use_lds = bhi >= blo && (bhi - blo) < (uint32_t)SPLAT_WIN;
       if (use_lds) {
         const int span = (int)(bhi - blo) + 1;
@@ -129,15 +182,16 @@ __global__ void __launch_bounds__(SPLAT_THREADS) k_splat(SplatParams p) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < SPLAT_PPT; ++k)
-          if (key[k]) atomicMax(&s_win[mc[k] - blo], key[k]);
+          if (key[k]) {
+            const uint32_t mc = spread16((uint32_t)gxs[k]) | (spread16((uint32_t)gys[k]) << 1);
+            atomicMax(&s_win[mc - blo], key[k]);
+          }
         __syncthreads();
         for (int w = tid; w < span; w += SPLAT_THREADS) {
           const unsigned long long kv = s_win[w];
           if (!kv) continue;
           const uint32_t code = blo + (uint32_t)w;
-          const int gx = (int)compact16(code), gy = (int)compact16(code >> 1);
-          const int64_t cell = cell_of(p, gx, gy);
-          atomicMax(&p.keys[cell], kv);
+          atomicMax(&p.keys[cell_of(p, (int)compact16(code), (int)compact16(code >> 1))], kv);
         }
       }
       __syncthreads();
@@ -148,12 +202,15 @@ __global__ void __launch_bounds__(SPLAT_THREADS) k_splat(SplatParams p) {
         if (key[k]) atomicMax(&p.keys[cell_of(p, gxs[k], gys[k])], key[k]);
     }
   }
-  // one atomic per workgroup for the dropped count
-  if (tid == 0) s_drop = 0;
+  // one global atomic per workgroup for the dropped count
+  for (int o = 32; o > 0; o >>= 1) dropped += (unsigned long long)__shfl_xor((long long)dropped, o, 64);
+  if (lane == 0) s_drop[wave] = dropped;
   __syncthreads();
-  if (dropped) atomicAdd(&s_drop, dropped);
-  __syncthreads();
-  if (tid == 0 && s_drop) atomicAdd(p.n_dropped, s_drop);
+  if (tid == 0) {
+    unsigned long long d = 0;
+    for (int w = 0; w < SPLAT_THREADS / 64; ++w) d += s_drop[w];
+    if (d) atomicAdd(p.n_dropped, d);
+  }
 }
 
 __global__ void k_resolve(const unsigned long long* __restrict__ keys, int64_t n_cells, double scale_z,
@@ -191,6 +248,7 @@ int ls_resolve_impl(const LsGridInfo& gi, const uint64_t* keys, int32_t n_slots,
   const int64_t cells = (int64_t)n_slots * gi.res * gi.res;
   if (cells <= 0) return LS_OK;
   const int blocks = (int)std::min<int64_t>((cells + 255) / 256, 16384);
+  LS_TRACE("resolve", st);
   hipLaunchKernelGGL(k_resolve, dim3(blocks), dim3(256), 0, st, reinterpret_cast<const unsigned long long*>(keys),
                      cells, gi.scale_z, gi.offset_z, reinterpret_cast<float4*>(tex_inout));
   LS_LAUNCH_CHECK();
@@ -205,14 +263,18 @@ int ls_splat_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   p.oy = gi.oy;
   p.C = gi.C;
   p.res = gi.res;
+  p.inv_C = 1.0 / gi.C;
+  p.inv_res = 1.0 / gi.res;
   p.tiles_x = gi.tx;
   p.tiles_y = gi.ty;
   const int64_t gw = (int64_t)gi.tx * gi.res, gh = (int64_t)gi.ty * gi.res;
-  if (gw > 0x7fffffff || gh > 0x7fffffff) return LS_ERANGE;
+  if (gw * gi.C >= 0x7fffffffLL || gh * gi.C >= 0x7fffffffLL) return LS_ERANGE;
   p.gw = (int32_t)gw;
   p.gh = (int32_t)gh;
   p.n_slots = n_slots;
   p.morton_ok = (gw <= 65536 && gh <= 65536) ? 1 : 0;
+  auto al = [](const void* q, uintptr_t a) { return (reinterpret_cast<uintptr_t>(q) % a) == 0; };
+  p.vec_ok = (al(x, 8) && al(y, 8) && al(z, 8) && al(rgb, 4)) ? 1 : 0;
   p.n = n;
   p.x = x;
   p.y = y;
@@ -224,6 +286,7 @@ int ls_splat_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   if (n > 0) {
     const int64_t batches = (n + SPLAT_BATCH - 1) / SPLAT_BATCH;
     const int blocks = (int)std::min<int64_t>(batches, 8 * cus());
+    LS_TRACE("splat", st);
     hipLaunchKernelGGL(k_splat, dim3(blocks), dim3(SPLAT_THREADS), 0, st, p);
     LS_LAUNCH_CHECK();
   }

@@ -305,6 +305,7 @@ int ls_conv_f32(const ConvArgs& a, hipStream_t st) {
   const int cob = a.cout % 32 == 0 ? 32 : (a.cout % 16 == 0 ? 16 : (a.cout % 8 == 0 ? 8 : 4));
   if (a.cout % 4) return LS_ENOTIMPL;
   dim3 grid(nblk(npix), a.cout / cob);
+  LS_TRACE("conv_f32", st);
 #define LS_CONV_CASE(N)                                                                   \
   if (cob == N) {                                                                          \
     if (mask) hipLaunchKernelGGL((k_conv_f32<N, true>), grid, dim3(CT), 0, st, a);         \
@@ -318,6 +319,7 @@ int ls_conv_f32(const ConvArgs& a, hipStream_t st) {
 
 int ls_avgpool_f32(const float* in, float* out, int B, int H, int W, int C, hipStream_t st) {
   const int64_t n = (int64_t)B * (H / 2) * (W / 2) * (C / 4);
+  LS_TRACE("avgpool_f32", st);
   hipLaunchKernelGGL(k_avgpool_f32, dim3(nblk(n)), dim3(CT), 0, st, in, out, B, H, W, C);
   LS_LAUNCH_CHECK();
   return LS_OK;
@@ -326,12 +328,14 @@ int ls_avgpool_f32(const float* in, float* out, int B, int H, int W, int C, hipS
 int ls_head_epilogue(const float* head, const float* x, const double* cz, int B, int res, int pad, double r_m,
                      float* y_out, float* tex_out, hipStream_t st) {
   const int64_t n = (int64_t)B * res * res;
+  LS_TRACE("head_epilogue", st);
   hipLaunchKernelGGL(k_head_epilogue, dim3(nblk(n)), dim3(CT), 0, st, head, x, cz, B, res, pad, r_m, y_out, tex_out);
   LS_LAUNCH_CHECK();
   return LS_OK;
 }
 
 int ls_prep_weights(const float* w, float* wt, float* wd, hipStream_t st) {
+  LS_TRACE("prep_weights", st);
   hipLaunchKernelGGL(k_prep_weights, dim3(nblk(LS_NUM_PARAMS)), dim3(CT), 0, st, w, wt, wd);
   LS_LAUNCH_CHECK();
   return LS_OK;
@@ -341,6 +345,7 @@ int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st) {
   const int cin = a.src.a.c + a.src.b.c;
   const int64_t n = (int64_t)a.cout * 9 * cin + a.cout;
   dim3 grid(nblk(n), a.nchunk);
+  LS_TRACE("wgrad_f32", st);
   hipLaunchKernelGGL(k_wgrad_f32, grid, dim3(CT), 0, st, a);
   hipLaunchKernelGGL(k_reduce_partials, dim3(nblk(n)), dim3(CT), 0, st, a.partial, a.nchunk, n, grad_w_layer);
   LS_LAUNCH_CHECK();

@@ -145,6 +145,152 @@ __global__ void __launch_bounds__(64 * WAVES) k_conv_bf16(ConvArgsB A) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// LDS-staged variant: a workgroup owns a 16 x 16 output tile of one image.
+// The 18 x 18 x cin input patch (zero padded, upsampling / concatenation /
+// FP32->BF16 folded in) is loaded once into LDS with an odd number of 16-byte
+// units per pixel, so the 16 lanes of an MFMA row read 16 distinct bank
+// groups.  Each wave computes 4 output rows (4 MFMA row tiles of 16 pixels)
+// for all output channels.  The result goes back through LDS so every lane
+// stores whole 16-byte channel groups, and the layers that feed an average
+// pool also write the pooled 8 x 8 tile.
+constexpr int TT = 16;       // output tile side
+constexpr int PT = TT + 2;   // input patch side
+
+struct ConvTileArgs {
+  ConvSrc src;
+  int B, H, W;           // input plane (zero padding outside)
+  int y0, x0, Ho, Wo;    // output window inside the plane
+  int tiles_x, tiles_y;  // output tiles per image
+  const uint16_t* wp;
+  int Kpad;
+  const float* bias;
+  int cout;
+  int relu;
+  uint16_t* out_bf16;  // [B][Ho][Wo][cout] or null
+  float* out_f32;      // [B][Ho][Wo][cout] or null
+  uint16_t* pool_out;  // [B][Ho/2][Wo/2][cout] or null (Ho, Wo multiples of 16)
+};
+
+__host__ __device__ __forceinline__ int patch_pitch(int cin) {
+  const int u = cin / 8;
+  return 8 * (u + ((u & 1) ? 0 : 1));  // bf16 elements per pixel, odd number of 16-byte units
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_conv_bf16_lds(ConvTileArgs A) {
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  uint16_t* s_in = reinterpret_cast<uint16_t*>(s_raw);
+  const int cin = A.src.a.c + A.src.b.c;
+  const int pitch = patch_pitch(cin);
+  const int per_img = A.tiles_x * A.tiles_y;
+  const int b = blockIdx.x / per_img;
+  const int t = blockIdx.x - b * per_img;
+  const int ty0 = (t / A.tiles_x) * TT, tx0 = (t % A.tiles_x) * TT;
+  const int iy0 = A.y0 + ty0 - 1, ix0 = A.x0 + tx0 - 1;
+  const int chunks = cin / 8;
+  for (int e = threadIdx.x; e < PT * PT * chunks; e += 256) {
+    const int pix = e / chunks, ch = e - pix * chunks;
+    const int py = pix / PT, px = pix - py * PT;
+    *reinterpret_cast<u16x8*>(s_in + pix * pitch + ch * 8) = load8(A.src, b, iy0 + py, ix0 + px, ch * 8, A.H, A.W);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int K = 9 * cin, KS = A.Kpad / 32;
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = ks * 32 + 8 * g;
+    bf16x8 bfr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+      bfr[nt] = __builtin_bit_cast(bf16x8,
+                                   *reinterpret_cast<const u16x8*>(A.wp + (int64_t)(nt * 16 + r16) * A.Kpad + k));
+    const bool kv = k < K;
+    const int tap = kv ? k / cin : 0;
+    const int ci = k - tap * cin;
+    const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+    const uint16_t* base = s_in + ((wave * 4 + ky) * PT + r16 + kx) * pitch + ci;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (kv) a = *reinterpret_cast<const u16x8*>(base + mt * PT * pitch);
+      const bf16x8 ab = __builtin_bit_cast(bf16x8, a);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bfr[nt], acc[mt][nt], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // the patch is dead; the same LDS now holds the output tile
+  const int cout = A.cout;
+  if (A.out_f32) {
+    float* s_of = reinterpret_cast<float*>(s_raw);
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int co = nt * 16 + r16;
+      if (co >= cout) continue;
+      const float bias = A.bias ? A.bias[co] : 0.f;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float v = acc[mt][nt][r] + bias;
+          if (A.relu) v = fmaxf(v, 0.f);
+          s_of[((wave * 4 + mt) * TT + 4 * g + r) * cout + co] = v;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < TT * TT * cout / 4; e += 256) {
+      const int pix = e / (cout / 4), c4 = e - pix * (cout / 4);
+      const int oy = ty0 + pix / TT, ox = tx0 + pix % TT;
+      if (oy >= A.Ho || ox >= A.Wo) continue;
+      *reinterpret_cast<float4*>(A.out_f32 + (((int64_t)b * A.Ho + oy) * A.Wo + ox) * cout + 4 * c4) =
+          *reinterpret_cast<const float4*>(s_of + pix * cout + 4 * c4);
+    }
+    return;
+  }
+  uint16_t* s_o = reinterpret_cast<uint16_t*>(s_raw);
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int co = nt * 16 + r16;
+    if (co >= cout) continue;
+    const float bias = A.bias ? A.bias[co] : 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[mt][nt][r] + bias;
+        if (A.relu) v = fmaxf(v, 0.f);
+        s_o[((wave * 4 + mt) * TT + 4 * g + r) * cout + co] = f2bf(v);
+      }
+  }
+  __syncthreads();
+  const int c8n = cout / 8;
+  if (A.out_bf16)
+    for (int e = threadIdx.x; e < TT * TT * c8n; e += 256) {
+      const int pix = e / c8n, c8 = e - pix * c8n;
+      const int oy = ty0 + pix / TT, ox = tx0 + pix % TT;
+      if (oy >= A.Ho || ox >= A.Wo) continue;
+      *reinterpret_cast<u16x8*>(A.out_bf16 + (((int64_t)b * A.Ho + oy) * A.Wo + ox) * cout + 8 * c8) =
+          *reinterpret_cast<const u16x8*>(s_o + pix * cout + 8 * c8);
+    }
+  if (A.pool_out) {
+    const int Hp = A.Ho / 2, Wp = A.Wo / 2;
+    for (int e = threadIdx.x; e < (TT / 2) * (TT / 2) * cout; e += 256) {
+      const int pp = e / cout, c = e - pp * cout;
+      const int py = pp / (TT / 2), px = pp % (TT / 2);
+      const uint16_t* q = s_o + ((2 * py) * TT + 2 * px) * cout + c;
+      const float s = (bf2f(q[0]) + bf2f(q[cout])) + (bf2f(q[TT * cout]) + bf2f(q[TT * cout + cout]));
+      const int oy = ty0 / 2 + py, ox = tx0 / 2 + px;
+      A.pool_out[(((int64_t)b * Hp + oy) * Wp + ox) * cout + c] = f2bf(0.25f * s);
+    }
+  }
+}
+
 __global__ void k_avgpool_bf16(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int B, int H, int W, int C) {
   const int64_t n = (int64_t)B * (H / 2) * (W / 2) * C;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -203,6 +349,7 @@ int ls_pack_bf16(const float* w, uint16_t* out, int64_t n, hipStream_t st) {
 
 int ls_bf16_prep_weights(const uint16_t* w_bf16, uint16_t* packed, hipStream_t st) {
   const int64_t n = (int64_t)ls_bf16_packed_total();
+  LS_TRACE("pack_bf16", st);
   hipLaunchKernelGGL(k_pack_weights_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w_bf16, packed);
   LS_LAUNCH_CHECK();
   return LS_OK;
@@ -233,10 +380,50 @@ int conv_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* packed, con
   const int64_t per_block = 16 * MT * WAVES;
   dim3 grid((unsigned)((npix + per_block - 1) / per_block));
   const int nt = (a.cout + 15) / 16;
+  LS_TRACE("conv_bf16", st);
   switch (nt) {
     case 1: hipLaunchKernelGGL(k_conv_bf16<1>, grid, dim3(64 * WAVES), 0, st, a); break;
     case 2: hipLaunchKernelGGL(k_conv_bf16<2>, grid, dim3(64 * WAVES), 0, st, a); break;
     case 4: hipLaunchKernelGGL(k_conv_bf16<4>, grid, dim3(64 * WAVES), 0, st, a); break;
+    default: return LS_ENOTIMPL;
+  }
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed, const float* w, uint16_t* out_bf16,
+                  float* out_f32, uint16_t* pool_out, int relu, int y0, int x0, int Ho, int Wo, hipStream_t st) {
+  ConvTileArgs a;
+  a.src = s;
+  a.B = B;
+  a.H = H;
+  a.W = H;
+  a.y0 = y0;
+  a.x0 = x0;
+  a.Ho = Ho;
+  a.Wo = Wo;
+  a.tiles_x = (Wo + TT - 1) / TT;
+  a.tiles_y = (Ho + TT - 1) / TT;
+  a.wp = packed + ls_bf16_packed_offset(l);
+  a.Kpad = ls_bf16_kpad(l);
+  a.bias = w + ls_layer_b_offset(l);
+  a.cout = LS_LAYERS[l].cout;
+  a.relu = relu;
+  a.out_bf16 = out_bf16;
+  a.out_f32 = out_f32;
+  a.pool_out = pool_out;
+  if (pool_out && (Ho % TT || Wo % TT)) return LS_ENOTIMPL;
+  const int cin = s.a.c + s.b.c;
+  const size_t patch = (size_t)PT * PT * patch_pitch(cin) * 2;
+  const size_t otile = (size_t)TT * TT * a.cout * (out_f32 ? 4 : 2);
+  const size_t lds = patch > otile ? patch : otile;
+  const dim3 grid((unsigned)(B * a.tiles_x * a.tiles_y));
+  const int nt = (a.cout + 15) / 16;
+  LS_TRACE("conv_bf16", st);
+  switch (nt) {
+    case 1: hipLaunchKernelGGL(k_conv_bf16_lds<1>, grid, dim3(256), lds, st, a); break;
+    case 2: hipLaunchKernelGGL(k_conv_bf16_lds<2>, grid, dim3(256), lds, st, a); break;
+    case 4: hipLaunchKernelGGL(k_conv_bf16_lds<4>, grid, dim3(256), lds, st, a); break;
     default: return LS_ENOTIMPL;
   }
   LS_LAUNCH_CHECK();
@@ -262,6 +449,7 @@ ConvSrc cs(SrcPart a, SrcPart b) {
 
 int pool_bf16(const uint16_t* in, uint16_t* out, int B, int H, int C, hipStream_t st) {
   const int64_t n = (int64_t)B * (H / 2) * (H / 2) * C;
+  LS_TRACE("avgpool_bf16", st);
   hipLaunchKernelGGL(k_avgpool_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, in, out, B, H, H, C);
   LS_LAUNCH_CHECK();
   return LS_OK;
@@ -294,25 +482,40 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   uint16_t* A10 = A9 + 16 * f * B;
   SrcPart X = src_plain(x, 8, R, R, 8, 0, nullptr);
   const SrcPart none = src_none();
-  auto full = [&](const ConvSrc& s, int H, int l, uint16_t* out) {
-    return conv_bf16(s, B, H, l, packed, w, out, nullptr, 1, 0, 0, H, H, st);
+  // per layer: tiling variant 0 = direct (A from global memory), 1 = LDS-staged tile (default)
+  auto variant = [&](int l) {
+    const int c = ls_conv_config_get(l, LS_BF16, 0);
+    return c < 0 ? 1 : c;
+  };
+  // a layer feeding an average pool writes the pooled tensor too when it uses the LDS tile
+  auto conv = [&](const ConvSrc& s, int H, int l, uint16_t* out, uint16_t* pooled) -> int {
+    if (variant(l) == 1) {
+      const bool fuse = pooled && H % TT == 0;
+      LS_TRYB(conv_bf16_lds(s, B, H, l, packed, w, out, nullptr, fuse ? pooled : nullptr, 1, 0, 0, H, H, st));
+      if (pooled && !fuse) return pool_bf16(out, pooled, B, H, LS_LAYERS[l].cout, st);
+      return LS_OK;
+    }
+    LS_TRYB(conv_bf16(s, B, H, l, packed, w, out, nullptr, 1, 0, 0, H, H, st));
+    if (pooled) return pool_bf16(out, pooled, B, H, LS_LAYERS[l].cout, st);
+    return LS_OK;
   };
   SrcPart u6 = bpart(A6, 64, R4);
   u6.up = 1;
   SrcPart u8 = bpart(A8, 32, R2);
   u8.up = 1;
-  LS_TRYB(full(cs(X, none), R, 0, A1));
-  LS_TRYB(full(cs(bpart(A1, 16, R), none), R, 1, A2));
-  LS_TRYB(pool_bf16(A2, P1, B, R, 16, st));
-  LS_TRYB(full(cs(bpart(P1, 16, R2), none), R2, 2, A3));
-  LS_TRYB(full(cs(bpart(A3, 32, R2), none), R2, 3, A4));
-  LS_TRYB(pool_bf16(A4, P2, B, R2, 32, st));
-  LS_TRYB(full(cs(bpart(P2, 32, R4), none), R4, 4, A5));
-  LS_TRYB(full(cs(bpart(A5, 64, R4), none), R4, 5, A6));
-  LS_TRYB(full(cs(u6, bpart(A4, 32, R2)), R2, 6, A7));
-  LS_TRYB(full(cs(bpart(A7, 32, R2), none), R2, 7, A8));
-  LS_TRYB(full(cs(u8, bpart(A2, 16, R)), R, 8, A9));
-  LS_TRYB(full(cs(bpart(A9, 16, R), none), R, 9, A10));
+  LS_TRYB(conv(cs(X, none), R, 0, A1, nullptr));
+  LS_TRYB(conv(cs(bpart(A1, 16, R), none), R, 1, A2, P1));
+  LS_TRYB(conv(cs(bpart(P1, 16, R2), none), R2, 2, A3, nullptr));
+  LS_TRYB(conv(cs(bpart(A3, 32, R2), none), R2, 3, A4, P2));
+  LS_TRYB(conv(cs(bpart(P2, 32, R4), none), R4, 4, A5, nullptr));
+  LS_TRYB(conv(cs(bpart(A5, 64, R4), none), R4, 5, A6, nullptr));
+  LS_TRYB(conv(cs(u6, bpart(A4, 32, R2)), R2, 6, A7, nullptr));
+  LS_TRYB(conv(cs(bpart(A7, 32, R2), none), R2, 7, A8, nullptr));
+  LS_TRYB(conv(cs(u8, bpart(A2, 16, R)), R, 8, A9, nullptr));
+  LS_TRYB(conv(cs(bpart(A9, 16, R), none), R, 9, A10, nullptr));
+  if (variant(10) == 1)
+    return conv_bf16_lds(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,
+                         gi.res, gi.res, st);
   return conv_bf16(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, 0, gi.pad, gi.pad, gi.res, gi.res,
                    st);
 }
