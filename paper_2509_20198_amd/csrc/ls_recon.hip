@@ -35,8 +35,8 @@
 namespace {
 
 constexpr int RB = 512;                  // threads per recon workgroup
-constexpr int LDS_INTS = 19456;          // 76 KB of LDS per recon workgroup (two per CU)
-constexpr int MAXG = 90;                 // max buckets per side
+constexpr int LDS_INTS = 16000;          // 62.5 KiB of LDS per recon workgroup
+constexpr int MAXG = 88;                 // max buckets per side
 constexpr int MAXB = MAXG * MAXG;        // max buckets
 static_assert(2 * (MAXB + 1) <= LDS_INTS, "bucket offsets must fit twice in the recon LDS");
 constexpr int STAR_MAX_STEPS = 1024;     // safeguard on one point's star walk
@@ -163,9 +163,9 @@ __global__ void __launch_bounds__(RB) k_bin_sort(const int32_t* __restrict__ bin
   __shared__ int32_t s_buf[SORT_LDS];
   if (flags[0]) return;
   for (int k = blockIdx.x; k < n_tiles; k += gridDim.x) {
-    const int32_t off = bin_off[k];
-    const int32_t cnt = bin_off[k + 1] - off;
-    if (cnt <= 1) continue;
+    const int32_t off = __builtin_amdgcn_readfirstlane(bin_off[k]);
+    const int32_t cnt = __builtin_amdgcn_readfirstlane(bin_off[k + 1]) - off;
+    if (cnt <= 1) continue;  // uniform: k comes from blockIdx, the counts are readfirstlane'd
     int n2 = 1;
     while (n2 < cnt) n2 <<= 1;
     int32_t* buf = n2 <= SORT_LDS ? s_buf : scratch + 2 * (int64_t)off;
@@ -517,7 +517,7 @@ __global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
   // canonical coordinates; the canonical bucket offsets sit at the end
   __shared__ int s_mem[LDS_INTS];
   __shared__ int s_tmp[RB / 64 + 1];
-  __shared__ int s_tile;
+  __shared__ int s_hdr[5];  // tile index, flags, bin offset, bin count, tile id
   __shared__ int s_flags;
   __shared__ double s_cz;
   const int tid = threadIdx.x;
@@ -526,234 +526,247 @@ __global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
   uint64_t* __restrict__ fm = P.facemap + (int64_t)blockIdx.x * RR;
   int32_t* __restrict__ nn = P.nnidx + (int64_t)blockIdx.x * RR;
   const bool cap_overflow = P.flags[0] != 0;
+  // Control flow below depends only on values that thread 0 fetches and
+  // broadcasts through LDS, read back with readfirstlane so the compiler
+  // sees them as uniform: every barrier then stays in uniform control flow
+  // and the loop has a single back edge (an earlier form with a `continue`
+  // let the compiler re-enter the barriers without the queue fetch).
   for (;;) {
-    if (tid == 0) s_tile = atomicAdd(P.queue, 1);
+    if (tid == 0) {
+      const int kk = atomicAdd(P.queue, 1);
+      s_hdr[0] = kk;
+      if (kk < P.n_tiles) {
+        int f = cap_overflow ? LS_TILE_CAP : 0;
+        f |= P.status[kk] & LS_TILE_BADID;
+        const int32_t o = P.bin_off[kk];
+        s_hdr[1] = f;
+        s_hdr[2] = o;
+        s_hdr[3] = (f & (LS_TILE_CAP | LS_TILE_BADID)) ? 0 : P.bin_off[kk + 1] - o;
+        s_hdr[4] = P.tile_list[kk];
+      }
+    }
     __syncthreads();
-    const int k = s_tile;
-    __syncthreads();
+    const int k = __builtin_amdgcn_readfirstlane(s_hdr[0]);
     if (k >= P.n_tiles) break;
-    const int32_t t = P.tile_list[k];
-    int flags = 0;
-    if (cap_overflow) flags |= LS_TILE_CAP;
-    const int prev = P.status[k];
-    flags |= prev & LS_TILE_BADID;
-    const int32_t off = P.bin_off[k];
-    const int32_t cnt = (flags & (LS_TILE_CAP | LS_TILE_BADID)) ? 0 : P.bin_off[k + 1] - off;
+    const int flags = __builtin_amdgcn_readfirstlane(s_hdr[1]);
+    const int32_t off = __builtin_amdgcn_readfirstlane(s_hdr[2]);
+    const int32_t cnt = __builtin_amdgcn_readfirstlane(s_hdr[3]);
+    const int32_t t = __builtin_amdgcn_readfirstlane(s_hdr[4]);
     if (cnt == 0) {
       write_zero_tile(P, k);
       if (tid == 0) {
         P.cz_out[k] = 0.0;
         P.status[k] = flags | LS_TILE_EMPTY;
       }
-      continue;
-    }
-    const int64_t cx = P.ox + (int64_t)(t % P.tiles_x) * P.S + P.S / 2;
-    const int64_t cy = P.oy + (int64_t)(t / P.tiles_x) * P.S + P.S / 2;
-    int G = 1;
-    {
-      const int want = (int)sqrtf((float)cnt * 0.5f);
-      G = want < 1 ? 1 : (want > MAXG ? MAXG : want);
-    }
-    const int NB = G * G;
-    int* s_b = s_mem;
-    int* s_k = s_mem + LDS_INTS - (NB + 1);
-    const bool uv_lds = 2 * cnt <= LDS_INTS - (NB + 1);
-    // ---- a. gather + bucket histogram
-    for (int b = tid; b <= NB; b += RB) s_b[b] = 0;
-    if (tid == 0) s_flags = 0;
-    __syncthreads();
-    for (int e = tid; e < cnt; e += RB) {
-      const int32_t gi = P.bin_idx[off + e];
-      const int u = (int)((int64_t)P.x[gi] - cx), v = (int)((int64_t)P.y[gi] - cy);
-      P.su[off + e] = u;
-      P.sv[off + e] = v;
-      P.sz[off + e] = P.z[gi];
-      const uint16_t* c3 = P.rgb + 3 * (int64_t)gi;
-      P.srgb[off + e] = (uint64_t)c3[0] | ((uint64_t)c3[1] << 16) | ((uint64_t)c3[2] << 32);
-      const int b = bucket_1d(v + H, G, W2) * G + bucket_1d(u + H, G, W2);
-      P.sslot[off + e] = atomicAdd(&s_b[b], 1);
-    }
-    __syncthreads();
-    block_scan_excl(s_b, NB + 1, s_tmp);
-    for (int e = tid; e < cnt; e += RB) {
-      const int u = P.su[off + e], v = P.sv[off + e];
-      const int b = bucket_1d(v + H, G, W2) * G + bucket_1d(u + H, G, W2);
-      const int pos = off + s_b[b] + P.sslot[off + e];
-      P.tu[pos] = u;
-      P.tv[pos] = v;
-      P.tz[pos] = P.sz[off + e];
-      P.trgb[pos] = P.srgb[off + e];
-    }
-    __syncthreads();
-    // ---- b. per-bucket sort + dedupe
-    if (tid == 0) s_k[NB] = 0;
-    for (int b = tid; b < NB; b += RB) {
-      const int lo = off + s_b[b], hi = off + s_b[b + 1];
-      for (int i = lo + 1; i < hi; ++i) {
-        const int u = P.tu[i], v = P.tv[i], zz = P.tz[i];
-        const uint64_t c = P.trgb[i];
-        int j = i - 1;
-        while (j >= lo && pt_less(u, v, zz, c, P.tu[j], P.tv[j], P.tz[j], P.trgb[j])) {
-          P.tu[j + 1] = P.tu[j];
-          P.tv[j + 1] = P.tv[j];
-          P.tz[j + 1] = P.tz[j];
-          P.trgb[j + 1] = P.trgb[j];
-          --j;
-        }
-        P.tu[j + 1] = u;
-        P.tv[j + 1] = v;
-        P.tz[j + 1] = zz;
-        P.trgb[j + 1] = c;
+    } else {
+      const int64_t cx = P.ox + (int64_t)(t % P.tiles_x) * P.S + P.S / 2;
+      const int64_t cy = P.oy + (int64_t)(t / P.tiles_x) * P.S + P.S / 2;
+      int G = 1;
+      {
+        const int want = (int)sqrtf((float)cnt * 0.5f);
+        G = want < 1 ? 1 : (want > MAXG ? MAXG : want);
       }
-      int kept = 0;
-      for (int i = lo; i < hi; ++i)
-        if (i == lo || P.tu[i] != P.tu[i - 1] || P.tv[i] != P.tv[i - 1]) ++kept;
-      s_k[b] = kept;
-    }
-    __syncthreads();
-    const int m = block_scan_excl(s_k, NB + 1, s_tmp);
-    for (int b = tid; b < NB; b += RB) {
-      const int lo = off + s_b[b], hi = off + s_b[b + 1];
-      int w = off + s_k[b];
-      for (int i = lo; i < hi; ++i)
-        if (i == lo || P.tu[i] != P.tu[i - 1] || P.tv[i] != P.tv[i - 1]) {
-          P.cuv[w] = make_int2(P.tu[i], P.tv[i]);
-          P.sz[w] = P.tz[i];
-          P.srgb[w] = P.trgb[i];
-          ++w;
-        }
-    }
-    __syncthreads();
-    int2* s_uv = reinterpret_cast<int2*>(s_mem);
-    if (uv_lds)
-      for (int p = tid; p < m; p += RB) s_uv[p] = P.cuv[off + p];
-    __syncthreads();
-    Tile T;
-    T.uv = uv_lds ? s_uv : P.cuv + off;
-    T.boff = s_k;
-    T.G = G;
-    T.H = H;
-    T.W2 = W2;
-    T.bw = (double)W2 / G;
-    const int32_t* Tz = P.sz + off;
-    const uint64_t* Tc = P.srgb + off;
-    // ---- c. nearest point per texel; face map reset
-    const int q0 = -H + C / 2;
-    for (int tt = tid; tt < RR; tt += RB) {
-      const int i = tt / R, j = tt - i * R;
-      nn[tt] = ring_nearest(T, q0 + j * C, q0 + i * C, -1);
-      fm[tt] = FACE_NONE;
-    }
-    // collinearity check
-    bool noncol = false;
-    if (m >= 3) {
-      const int2 p0 = T.uv[0], p1 = T.uv[1];
-      for (int p = tid; p < m; p += RB) {
-        const int2 q = T.uv[p];
-        if (orient_d(p0.x, p0.y, p1.x, p1.y, q.x, q.y) != 0.0) noncol = true;
+      const int NB = G * G;
+      int* s_b = s_mem;
+      int* s_k = s_mem + LDS_INTS - (NB + 1);
+      const bool uv_lds = 2 * cnt <= LDS_INTS - (NB + 1);
+      // ---- a. gather + bucket histogram
+      for (int b = tid; b <= NB; b += RB) s_b[b] = 0;
+      if (tid == 0) s_flags = 0;
+      __syncthreads();
+      for (int e = tid; e < cnt; e += RB) {
+        const int32_t gi = P.bin_idx[off + e];
+        const int u = (int)((int64_t)P.x[gi] - cx), v = (int)((int64_t)P.y[gi] - cy);
+        P.su[off + e] = u;
+        P.sv[off + e] = v;
+        P.sz[off + e] = P.z[gi];
+        const uint16_t* c3 = P.rgb + 3 * (int64_t)gi;
+        P.srgb[off + e] = (uint64_t)c3[0] | ((uint64_t)c3[1] << 16) | ((uint64_t)c3[2] << 32);
+        const int b = bucket_1d(v + H, G, W2) * G + bucket_1d(u + H, G, W2);
+        P.sslot[off + e] = atomicAdd(&s_b[b], 1);
       }
-    }
-    // face keys pack three point indices in 21 bits each
-    const bool has_dt = (__syncthreads_or(noncol) != 0) && m < (1 << 21);
-    if (m >= (1 << 21) && tid == 0) atomicOr(&s_flags, LS_TILE_DEGENERATE);
-    // ---- d. Delaunay stars, rasterised into the face map
-    if (has_dt) {
-      for (int a = tid; a < m; a += RB) {
-        const int b0 = ring_nearest(T, T.uv[a].x, T.uv[a].y, a);
-        int b = b0;
-        bool closed = false;
-        int steps = 0;
-        int prev_b = -1;  // second vertex of the last CCW triangle
-        uint64_t hull_key = FACE_NONE;
-        int hull_b = -1;
-        while (steps++ < STAR_MAX_STEPS) {
-          const int c = third_left(T, a, b);
-          if (c < 0) {
-            hull_b = b;
-            if (prev_b >= 0) hull_key = face_key(a, prev_b, b);
-            break;
+      __syncthreads();
+      block_scan_excl(s_b, NB + 1, s_tmp);
+      for (int e = tid; e < cnt; e += RB) {
+        const int u = P.su[off + e], v = P.sv[off + e];
+        const int b = bucket_1d(v + H, G, W2) * G + bucket_1d(u + H, G, W2);
+        const int pos = off + s_b[b] + P.sslot[off + e];
+        P.tu[pos] = u;
+        P.tv[pos] = v;
+        P.tz[pos] = P.sz[off + e];
+        P.trgb[pos] = P.srgb[off + e];
+      }
+      __syncthreads();
+      // ---- b. per-bucket sort + dedupe
+      if (tid == 0) s_k[NB] = 0;
+      for (int b = tid; b < NB; b += RB) {
+        const int lo = off + s_b[b], hi = off + s_b[b + 1];
+        for (int i = lo + 1; i < hi; ++i) {
+          const int u = P.tu[i], v = P.tv[i], zz = P.tz[i];
+          const uint64_t c = P.trgb[i];
+          int j = i - 1;
+          while (j >= lo && pt_less(u, v, zz, c, P.tu[j], P.tv[j], P.tz[j], P.trgb[j])) {
+            P.tu[j + 1] = P.tu[j];
+            P.tv[j + 1] = P.tv[j];
+            P.tz[j + 1] = P.tz[j];
+            P.trgb[j + 1] = P.trgb[j];
+            --j;
           }
-          if (a < b && a < c) raster_triangle(T, a, b, c, C, R, fm);
-          prev_b = b;
-          b = c;
-          if (b == b0) {
-            closed = true;
-            break;
-          }
+          P.tu[j + 1] = u;
+          P.tv[j + 1] = v;
+          P.tz[j + 1] = zz;
+          P.trgb[j + 1] = c;
         }
-        if (!closed && steps <= STAR_MAX_STEPS) {
-          b = b0;
-          bool first = true;
+        int kept = 0;
+        for (int i = lo; i < hi; ++i)
+          if (i == lo || P.tu[i] != P.tu[i - 1] || P.tv[i] != P.tv[i - 1]) ++kept;
+        s_k[b] = kept;
+      }
+      __syncthreads();
+      const int m = __builtin_amdgcn_readfirstlane(block_scan_excl(s_k, NB + 1, s_tmp));
+      for (int b = tid; b < NB; b += RB) {
+        const int lo = off + s_b[b], hi = off + s_b[b + 1];
+        int w = off + s_k[b];
+        for (int i = lo; i < hi; ++i)
+          if (i == lo || P.tu[i] != P.tu[i - 1] || P.tv[i] != P.tv[i - 1]) {
+            P.cuv[w] = make_int2(P.tu[i], P.tv[i]);
+            P.sz[w] = P.tz[i];
+            P.srgb[w] = P.trgb[i];
+            ++w;
+          }
+      }
+      __syncthreads();
+      int2* s_uv = reinterpret_cast<int2*>(s_mem);
+      if (uv_lds)
+        for (int p = tid; p < m; p += RB) s_uv[p] = P.cuv[off + p];
+      __syncthreads();
+      Tile T;
+      T.uv = uv_lds ? s_uv : P.cuv + off;
+      T.boff = s_k;
+      T.G = G;
+      T.H = H;
+      T.W2 = W2;
+      T.bw = (double)W2 / G;
+      const int32_t* Tz = P.sz + off;
+      const uint64_t* Tc = P.srgb + off;
+      // ---- c. nearest point per texel; face map reset
+      const int q0 = -H + C / 2;
+      for (int tt = tid; tt < RR; tt += RB) {
+        const int i = tt / R, j = tt - i * R;
+        nn[tt] = ring_nearest(T, q0 + j * C, q0 + i * C, -1);
+        fm[tt] = FACE_NONE;
+      }
+      // collinearity check
+      bool noncol = false;
+      if (m >= 3) {
+        const int2 p0 = T.uv[0], p1 = T.uv[1];
+        for (int p = tid; p < m; p += RB) {
+          const int2 q = T.uv[p];
+          if (orient_d(p0.x, p0.y, p1.x, p1.y, q.x, q.y) != 0.0) noncol = true;
+        }
+      }
+      // face keys pack three point indices in 21 bits each
+      const bool has_dt = (__builtin_amdgcn_readfirstlane(__syncthreads_or(noncol)) != 0) && m < (1 << 21);
+      if (m >= (1 << 21) && tid == 0) atomicOr(&s_flags, LS_TILE_DEGENERATE);
+      // ---- d. Delaunay stars, rasterised into the face map
+      if (has_dt) {
+        for (int a = tid; a < m; a += RB) {
+          const int b0 = ring_nearest(T, T.uv[a].x, T.uv[a].y, a);
+          int b = b0;
+          bool closed = false;
+          int steps = 0;
+          int prev_b = -1;  // second vertex of the last CCW triangle
+          uint64_t hull_key = FACE_NONE;
+          int hull_b = -1;
           while (steps++ < STAR_MAX_STEPS) {
-            const int c = third_left(T, b, a);  // triangle (b, a, c)
-            if (c < 0) break;
-            if (first && hull_key == FACE_NONE) hull_key = face_key(b, a, c);
-            first = false;
-            if (a < b && a < c) raster_triangle(T, b, a, c, C, R, fm);
+            const int c = third_left(T, a, b);
+            if (c < 0) {
+              hull_b = b;
+              if (prev_b >= 0) hull_key = face_key(a, prev_b, b);
+              break;
+            }
+            if (a < b && a < c) raster_triangle(T, a, b, c, C, R, fm);
+            prev_b = b;
             b = c;
+            if (b == b0) {
+              closed = true;
+              break;
+            }
           }
+          if (!closed && steps <= STAR_MAX_STEPS) {
+            b = b0;
+            bool first = true;
+            while (steps++ < STAR_MAX_STEPS) {
+              const int c = third_left(T, b, a);  // triangle (b, a, c)
+              if (c < 0) break;
+              if (first && hull_key == FACE_NONE) hull_key = face_key(b, a, c);
+              first = false;
+              if (a < b && a < c) raster_triangle(T, b, a, c, C, R, fm);
+              b = c;
+            }
+          }
+          if (steps > STAR_MAX_STEPS) atomicOr(&s_flags, LS_TILE_DEGENERATE);
+          if (hull_b >= 0 && hull_key != FACE_NONE) raster_hull_edge(T, a, hull_b, hull_key, C, R, fm);
         }
-        if (steps > STAR_MAX_STEPS) atomicOr(&s_flags, LS_TILE_DEGENERATE);
-        if (hull_b >= 0 && hull_key != FACE_NONE) raster_hull_edge(T, a, hull_b, hull_key, C, R, fm);
       }
-    }
-    __syncthreads();
-    // ---- e. interpolation, normalisation, output
-    auto lin_value = [&](int tt, double* out4) {
-      const int i = tt / R, j = tt - i * R;
-      const uint64_t f = fm[tt];
-      if (f == FACE_NONE) {
+      __syncthreads();
+      // ---- e. interpolation, normalisation, output
+      auto lin_value = [&](int tt, double* out4) {
+        const int i = tt / R, j = tt - i * R;
+        const uint64_t f = fm[tt];
+        if (f == FACE_NONE) {
+          const int p = nn[tt];
+          out4[0] = (double)Tz[p] * P.scale_z + P.offset_z;
+          const uint64_t c = Tc[p];
+          out4[1] = (double)(c & 0xFFFF);
+          out4[2] = (double)((c >> 16) & 0xFFFF);
+          out4[3] = (double)((c >> 32) & 0xFFFF);
+          return;
+        }
+        const int a = (int)(f >> 42), b = (int)((f >> 21) & 0x1FFFFF), c = (int)(f & 0x1FFFFF);
+        const int2 A = T.uv[a], B = T.uv[b], Cc = T.uv[c];
+        const double qx = q0 + j * C, qy = q0 + i * C;
+        const double ob = orient_d(Cc.x, Cc.y, A.x, A.y, qx, qy);
+        const double oc = orient_d(A.x, A.y, B.x, B.y, qx, qy);
+        const double O = orient_d(A.x, A.y, B.x, B.y, Cc.x, Cc.y);
+        const double lb = ob / O, lc = oc / O;
+        const double za = Tz[a], zb = Tz[b], zc = Tz[c];
+        const double h = za + lb * (zb - za) + lc * (zc - za);
+        out4[0] = h * P.scale_z + P.offset_z;
+        const uint64_t ca = Tc[a], cb = Tc[b], cc = Tc[c];
+        for (int ch = 0; ch < 3; ++ch) {
+          const double va = (double)((ca >> (16 * ch)) & 0xFFFF), vb = (double)((cb >> (16 * ch)) & 0xFFFF),
+                       vc = (double)((cc >> (16 * ch)) & 0xFFFF);
+          out4[1 + ch] = va + lb * (vb - va) + lc * (vc - va);
+        }
+      };
+      if (tid == 0) {
+        double v4[4];
+        lin_value((R / 2) * R + R / 2, v4);
+        s_cz = v4[0];
+      }
+      __syncthreads();
+      const double cz = s_cz;
+      float4* __restrict__ out = reinterpret_cast<float4*>(P.x_out + (int64_t)k * RR * 8);
+      for (int tt = tid; tt < RR; tt += RB) {
+        double lv[4];
+        lin_value(tt, lv);
         const int p = nn[tt];
-        out4[0] = (double)Tz[p] * P.scale_z + P.offset_z;
+        const double hn = (double)Tz[p] * P.scale_z + P.offset_z;
         const uint64_t c = Tc[p];
-        out4[1] = (double)(c & 0xFFFF);
-        out4[2] = (double)((c >> 16) & 0xFFFF);
-        out4[3] = (double)((c >> 32) & 0xFFFF);
-        return;
+        const double k65 = 1.0 / 65535.0;
+        out[2 * tt] = make_float4((float)((lv[0] - cz) * P.inv_r), (float)((hn - cz) * P.inv_r), (float)(lv[1] * k65),
+                                  (float)(lv[2] * k65));
+        out[2 * tt + 1] = make_float4((float)(lv[3] * k65), (float)((double)(c & 0xFFFF) * k65),
+                                      (float)((double)((c >> 16) & 0xFFFF) * k65),
+                                      (float)((double)((c >> 32) & 0xFFFF) * k65));
       }
-      const int a = (int)(f >> 42), b = (int)((f >> 21) & 0x1FFFFF), c = (int)(f & 0x1FFFFF);
-      const int2 A = T.uv[a], B = T.uv[b], Cc = T.uv[c];
-      const double qx = q0 + j * C, qy = q0 + i * C;
-      const double ob = orient_d(Cc.x, Cc.y, A.x, A.y, qx, qy);
-      const double oc = orient_d(A.x, A.y, B.x, B.y, qx, qy);
-      const double O = orient_d(A.x, A.y, B.x, B.y, Cc.x, Cc.y);
-      const double lb = ob / O, lc = oc / O;
-      const double za = Tz[a], zb = Tz[b], zc = Tz[c];
-      const double h = za + lb * (zb - za) + lc * (zc - za);
-      out4[0] = h * P.scale_z + P.offset_z;
-      const uint64_t ca = Tc[a], cb = Tc[b], cc = Tc[c];
-      for (int ch = 0; ch < 3; ++ch) {
-        const double va = (double)((ca >> (16 * ch)) & 0xFFFF), vb = (double)((cb >> (16 * ch)) & 0xFFFF),
-                     vc = (double)((cc >> (16 * ch)) & 0xFFFF);
-        out4[1 + ch] = va + lb * (vb - va) + lc * (vc - va);
-      }
-    };
-    if (tid == 0) {
-      double v4[4];
-      lin_value((R / 2) * R + R / 2, v4);
-      s_cz = v4[0];
-    }
-    __syncthreads();
-    const double cz = s_cz;
-    float4* __restrict__ out = reinterpret_cast<float4*>(P.x_out + (int64_t)k * RR * 8);
-    for (int tt = tid; tt < RR; tt += RB) {
-      double lv[4];
-      lin_value(tt, lv);
-      const int p = nn[tt];
-      const double hn = (double)Tz[p] * P.scale_z + P.offset_z;
-      const uint64_t c = Tc[p];
-      const double k65 = 1.0 / 65535.0;
-      out[2 * tt] = make_float4((float)((lv[0] - cz) * P.inv_r), (float)((hn - cz) * P.inv_r), (float)(lv[1] * k65),
-                                (float)(lv[2] * k65));
-      out[2 * tt + 1] = make_float4((float)(lv[3] * k65), (float)((double)(c & 0xFFFF) * k65),
-                                    (float)((double)((c >> 16) & 0xFFFF) * k65),
-                                    (float)((double)((c >> 32) & 0xFFFF) * k65));
-    }
     if (tid == 0) {
       P.cz_out[k] = cz;
       int st = flags | s_flags;
       if (!has_dt) st |= LS_TILE_NN_ONLY;
       P.status[k] = st;
+    }
     }
     __syncthreads();
   }

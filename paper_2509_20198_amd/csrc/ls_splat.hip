@@ -175,6 +175,10 @@ __global__ void __launch_bounds__(SPLAT_THREADS) k_splat(SplatParams p) {
         blo = min(blo, s_lo[w]);
         bhi = max(bhi, s_hi[w]);
       }
+      // uniform by construction; readfirstlane lets the compiler keep the
+      // barriers below in uniform control flow
+      blo = (uint32_t)__builtin_amdgcn_readfirstlane((int)blo);
+      bhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)bhi);
       use_lds = bhi >= blo && (bhi - blo) < (uint32_t)SPLAT_WIN;
       if (use_lds) {
         const int span = (int)(bhi - blo) + 1;

@@ -489,7 +489,8 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   };
   // a layer feeding an average pool writes the pooled tensor too when it uses the LDS tile
   auto conv = [&](const ConvSrc& s, int H, int l, uint16_t* out, uint16_t* pooled) -> int {
-    if (variant(l) == 1) {
+    const int cin_l = LS_LAYERS[l].cin;
+    if (variant(l) == 1 && (size_t)PT * PT * patch_pitch(cin_l) * 2 <= 65536) {
       const bool fuse = pooled && H % TT == 0;
       LS_TRYB(conv_bf16_lds(s, B, H, l, packed, w, out, nullptr, fuse ? pooled : nullptr, 1, 0, 0, H, H, st));
       if (pooled && !fuse) return pool_bf16(out, pooled, B, H, LS_LAYERS[l].cout, st);
@@ -513,7 +514,7 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   LS_TRYB(conv(cs(bpart(A7, 32, R2), none), R2, 7, A8, nullptr));
   LS_TRYB(conv(cs(u8, bpart(A2, 16, R)), R, 8, A9, nullptr));
   LS_TRYB(conv(cs(bpart(A9, 16, R), none), R, 9, A10, nullptr));
-  if (variant(10) == 1)
+  if (variant(10) == 1 && (size_t)PT * PT * patch_pitch(24) * 2 <= 65536)
     return conv_bf16_lds(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,
                          gi.res, gi.res, st);
   return conv_bf16(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, 0, gi.pad, gi.pad, gi.res, gi.res,

@@ -81,9 +81,6 @@ def test_pareto_counts_small_tiles():
     _compare(w.region, w.points.numpy(), w.tile_list)
 
 
-@pytest.mark.skip(reason="stopped making progress on the GPU with the 512-lane LDS-coordinate recon kernel; "
-                         "the CPU emulation of the same kernel finishes and matches the oracle, so no cause is "
-                         "shown yet and the case stays off the GPU (see DESIGN.md, known issues)")
 def test_edge_cases_empty_nn_only_duplicates():
     region = synth.Region(tiles_x=4, tiles_y=1)
     S = 64000
