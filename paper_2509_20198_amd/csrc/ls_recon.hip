@@ -278,52 +278,57 @@ __device__ int incircle_sos(const Tile& T, int a, int b, int c, int d, int2 pa, 
   return sgn_d(orient_d(pa.x, pa.y, pb.x, pb.y, pd.x, pd.y));
 }
 
-// Visit the buckets at Chebyshev ring r around (bx0, by0) that `keep`
-// accepts, then every point of those buckets.
-template <class K, class F>
-__device__ __forceinline__ void ring_visit(const Tile& T, int bx0, int by0, int r, K&& keep, F&& f) {
-  const int G = T.G;
-  const int ylo = by0 - r, yhi = by0 + r, xlo = bx0 - r, xhi = bx0 + r;
-  for (int by = ylo < 0 ? 0 : ylo; by <= (yhi < G ? yhi : G - 1); ++by) {
-    const bool full = (by == ylo || by == yhi);
-    const int step = full ? 1 : (xhi - xlo);
-    for (int bx = xlo; bx <= xhi; bx += (step > 0 ? step : 1)) {
-      if (bx < 0 || bx >= G) continue;
-      if (!keep(bx, by)) continue;
-      const int b = by * G + bx;
-      const int e = T.boff[b + 1];
-      for (int p = T.boff[b]; p < e; ++p) f(p);
-    }
-  }
-}
-
 __device__ __forceinline__ bool ring_covers_grid(const Tile& T, int bx0, int by0, int r) {
   return bx0 - r <= 0 && by0 - r <= 0 && bx0 + r >= T.G - 1 && by0 + r >= T.G - 1;
 }
 
 // Nearest canonical point to (qx, qy), ties by smallest (d^2, v, u); skips
-// point `skip`.  Returns -1 if no point.
+// point `skip`.  Returns -1 if no point.  Chebyshev rings of buckets around
+// q's bucket; once a candidate exists, buckets farther from q than it are
+// skipped, and the search stops when the candidate is closer than the
+// nearest side of the square visited so far.
 __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
-  const int bx0 = bucket_1d(qx + T.H, T.G, T.W2), by0 = bucket_1d(qy + T.H, T.G, T.W2);
+  const int G = T.G;
+  const int bx0 = bucket_1d(qx + T.H, G, T.W2), by0 = bucket_1d(qy + T.H, G, T.W2);
+  const double fx = qx + T.H, fy = qy + T.H;  // grid-local
   int best = -1;
   int64_t bd = 0;
   int bu = 0, bv = 0;
-  auto all = [](int, int) { return true; };
   for (int r = 0;; ++r) {
-    ring_visit(T, bx0, by0, r, all, [&](int p) {
-      if (p == skip) return;
-      const int2 q = T.uv[p];
-      const int64_t dx = q.x - qx, dy = q.y - qy;
-      const int64_t d = dx * dx + dy * dy;
-      if (best < 0 || d < bd || (d == bd && (q.y < bv || (q.y == bv && q.x < bu)))) {
-        best = p;
-        bd = d;
-        bu = q.x;
-        bv = q.y;
+    const int ylo = by0 - r, yhi = by0 + r, xlo = bx0 - r, xhi = bx0 + r;
+    for (int by = max(ylo, 0); by <= min(yhi, G - 1); ++by) {
+      const bool full = (by == ylo || by == yhi);
+      const int step = full ? 1 : (xhi - xlo);
+      for (int bx = xlo; bx <= xhi; bx += (step > 0 ? step : 1)) {
+        if (bx < 0 || bx >= G) continue;
+        if (best >= 0) {
+          // distance from q to the bucket rectangle, rounded outwards
+          const double x0 = floor(bx * T.bw) - 1.0, x1 = ceil((bx + 1) * T.bw) + 1.0;
+          const double y0 = floor(by * T.bw) - 1.0, y1 = ceil((by + 1) * T.bw) + 1.0;
+          const double dx = fmax(fmax(x0 - fx, fx - x1), 0.0), dy = fmax(fmax(y0 - fy, fy - y1), 0.0);
+          if (dx * dx + dy * dy > (double)bd) continue;
+        }
+        const int b = by * G + bx;
+        const int e = T.boff[b + 1];
+        for (int p = T.boff[b]; p < e; ++p) {
+          if (p == skip) continue;
+          const int2 q = T.uv[p];
+          const int64_t dx = q.x - qx, dy = q.y - qy;
+          const int64_t d = dx * dx + dy * dy;
+          if (best < 0 || d < bd || (d == bd && (q.y < bv || (q.y == bv && q.x < bu)))) {
+            best = p;
+            bd = d;
+            bu = q.x;
+            bv = q.y;
+          }
+        }
       }
-    });
+    }
     if (best >= 0) {
-      const double L = r * T.bw - 2.0;  // lower bound on the distance of unvisited points
+      // distance from q to the outside of the square of buckets visited
+      const double L = fmin(fmin(fx - floor((bx0 - r) * T.bw), ceil((bx0 + r + 1) * T.bw) - fx),
+                            fmin(fy - floor((by0 - r) * T.bw), ceil((by0 + r + 1) * T.bw) - fy)) -
+                       1.0;
       if (L > 0.0 && (double)bd < L * L) break;
     }
     if (ring_covers_grid(T, bx0, by0, r)) break;
@@ -331,57 +336,144 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
   return best;
 }
 
+// Bucket index range of the tile-local box [x0, x1] x [y0, y1] widened by
+// `slack` raw units, clamped to the grid.
+struct BucketBox {
+  int x0, x1, y0, y1;
+};
+__device__ __forceinline__ int bucket_clamped(const Tile& T, double w) {
+  const double c = fmin(fmax(w, (double)-T.H), (double)(T.H - 1));
+  return bucket_1d((int)c + T.H, T.G, T.W2);
+}
+__device__ __forceinline__ BucketBox bucket_box(const Tile& T, double x0, double x1, double y0, double y1,
+                                                double slack) {
+  BucketBox r;
+  r.x0 = bucket_clamped(T, floor(x0 - slack));
+  r.x1 = bucket_clamped(T, ceil(x1 + slack));
+  r.y0 = bucket_clamped(T, floor(y0 - slack));
+  r.y1 = bucket_clamped(T, ceil(y1 + slack));
+  return r;
+}
+
 // The third vertex of the Delaunay triangle on the left of edge a->b: the
 // first point met by a circle through a and b whose centre moves left.
 // Returns -1 if no point lies strictly left of a->b (a->b is a hull edge).
-// Buckets entirely on the right of the line, or (once a candidate exists)
-// entirely outside its circumcircle, are skipped.
+// Buckets are visited in Chebyshev rings around the midpoint, each ring
+// clipped to the bounding box of the region a better point could still lie
+// in: the window on the left of the line and, once a candidate exists, the
+// part of its circumcircle on that side (for a centre on the right this is
+// the thin cap between the chord and the parallel tangent).  Inside the box,
+// buckets entirely right of the line or outside the circle are skipped.
 __device__ int third_left(const Tile& T, int a, int b) {
   const int2 A = T.uv[a], B = T.uv[b];
   const int ax = A.x, ay = A.y, bx = B.x, by = B.y;
   const int mx = (ax + bx) >> 1, my = (ay + by) >> 1;
   const int bx0 = bucket_1d(mx + T.H, T.G, T.W2), by0 = bucket_1d(my + T.H, T.G, T.W2);
-  int best = -1;
-  int2 C = make_int2(0, 0);
-  double stop = 0.0, ocx = 0.0, ocy = 0.0, rho = 0.0;  // circle centre (tile-local) and radius
   const double fbx = bx - ax, fby = by - ay;
   const double bl = fbx * fbx + fby * fby;
-  auto keep = [&](int qx, int qy) {
+  // window [-H, H-1]^2 clipped to the closed left half-plane (corners on
+  // the line included, crossings rounded outwards by the slack below)
+  double hx0 = 1e300, hx1 = -1e300, hy0 = 1e300, hy1 = -1e300;
+  bool any_left = false;
+  {
+    const double lo = -T.H, hi = T.H - 1;
+    const double px[4] = {lo, hi, hi, lo}, py[4] = {lo, lo, hi, hi};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int j = (i + 1) & 3;
+      const double oi = orient_d(ax, ay, bx, by, px[i], py[i]), oj = orient_d(ax, ay, bx, by, px[j], py[j]);
+      any_left |= oi > 0.0;
+      if (oi >= 0.0) {
+        hx0 = fmin(hx0, px[i]);
+        hx1 = fmax(hx1, px[i]);
+        hy0 = fmin(hy0, py[i]);
+        hy1 = fmax(hy1, py[i]);
+      }
+      if ((oi > 0.0 && oj < 0.0) || (oi < 0.0 && oj > 0.0)) {
+        const double t = oi / (oi - oj);
+        const double qx = px[i] + t * (px[j] - px[i]), qy = py[i] + t * (py[j] - py[i]);
+        hx0 = fmin(hx0, qx);
+        hx1 = fmax(hx1, qx);
+        hy0 = fmin(hy0, qy);
+        hy1 = fmax(hy1, qy);
+      }
+    }
+  }
+  if (!any_left) return -1;
+  const BucketBox half = bucket_box(T, hx0, hx1, hy0, hy1, 2.0);
+  BucketBox bb = half;
+  int rmax = max(max(bx0 - bb.x0, bb.x1 - bx0), max(by0 - bb.y0, bb.y1 - by0));
+  int best = -1;
+  int2 C = make_int2(0, 0);
+  double ocx = 0.0, ocy = 0.0, rho = 0.0;  // circle centre (tile-local) and radius
+  auto visit = [&](int qx, int qy) {
     // bucket rectangle in tile-local coordinates, rounded outwards to integers
     const double x0 = floor(qx * T.bw) - T.H - 1.0, x1 = ceil((qx + 1) * T.bw) - T.H + 1.0;
     const double y0 = floor(qy * T.bw) - T.H - 1.0, y1 = ceil((qy + 1) * T.bw) - T.H + 1.0;
     const double o00 = orient_d(ax, ay, bx, by, x0, y0), o10 = orient_d(ax, ay, bx, by, x1, y0);
     const double o01 = orient_d(ax, ay, bx, by, x0, y1), o11 = orient_d(ax, ay, bx, by, x1, y1);
-    if (fmax(fmax(o00, o10), fmax(o01, o11)) <= 0.0) return false;
+    if (fmax(fmax(o00, o10), fmax(o01, o11)) <= 0.0) return;
     if (best >= 0) {
       const double dx = fmax(fmax(x0 - ocx, ocx - x1), 0.0), dy = fmax(fmax(y0 - ocy, ocy - y1), 0.0);
       const double lim = rho * (1.0 + 1e-9) + 2.0;
-      if (dx * dx + dy * dy > lim * lim) return false;
+      if (dx * dx + dy * dy > lim * lim) return;
     }
-    return true;
-  };
-  for (int r = 0;; ++r) {
-    ring_visit(T, bx0, by0, r, keep, [&](int p) {
-      if (p == a || p == b) return;
+    const int bi = qy * T.G + qx;
+    const int e = T.boff[bi + 1];
+    for (int p = T.boff[bi]; p < e; ++p) {
+      if (p == a || p == b) continue;
       const int2 P = T.uv[p];
-      if (orient_d(ax, ay, bx, by, P.x, P.y) <= 0.0) return;
-      if (best < 0 || incircle_sos(T, a, b, best, p, A, B, C, P) > 0) {
-        best = p;
-        C = P;
-        // circumcircle of (a, b, p) relative to a, and its reach from the midpoint
-        const double cx = P.x - ax, cy = P.y - ay;
-        const double cl = cx * cx + cy * cy;
-        const double D = 2.0 * (fbx * cy - fby * cx);
-        const double ox = (cy * bl - fby * cl) / D, oy = (fbx * cl - cx * bl) / D;
-        rho = sqrt(ox * ox + oy * oy);
-        ocx = ox + ax;
-        ocy = oy + ay;
-        const double dmx = ox - (mx - ax), dmy = oy - (my - ay);
-        stop = (sqrt(dmx * dmx + dmy * dmy) + rho) * (1.0 + 1e-9) + 2.0;
+      if (orient_d(ax, ay, bx, by, P.x, P.y) <= 0.0) continue;
+      if (best >= 0 && incircle_sos(T, a, b, best, p, A, B, C, P) <= 0) continue;
+      best = p;
+      C = P;
+      // circumcircle of (a, b, p) relative to a
+      const double cx = P.x - ax, cy = P.y - ay;
+      const double cl = cx * cx + cy * cy;
+      const double D = 2.0 * (fbx * cy - fby * cx);
+      const double ox = (cy * bl - fby * cl) / D, oy = (fbx * cl - cx * bl) / D;
+      rho = sqrt(ox * ox + oy * oy);
+      ocx = ox + ax;
+      ocy = oy + ay;
+      // signed distance of the centre from the line, > 0 on the left
+      const double ll = sqrt(bl);
+      const double dc = (fbx * oy - fby * ox) / ll;
+      double cx0, cx1, cy0, cy1;
+      if (dc <= 0.0) {
+        // sagitta rho - |dc| = (|ab|/2)^2 / (rho + |dc|), free of cancellation
+        const double h = bl / (4.0 * (rho - dc)) * (1.0 + 1e-9);
+        const double nx = -fby / ll * h, ny = fbx / ll * h;
+        cx0 = fmin(fmin(ax, bx), fmin(ax + nx, bx + nx));
+        cx1 = fmax(fmax(ax, bx), fmax(ax + nx, bx + nx));
+        cy0 = fmin(fmin(ay, by), fmin(ay + ny, by + ny));
+        cy1 = fmax(fmax(ay, by), fmax(ay + ny, by + ny));
+      } else {
+        cx0 = ocx - rho;
+        cx1 = ocx + rho;
+        cy0 = ocy - rho;
+        cy1 = ocy + rho;
       }
-    });
-    if (best >= 0 && r * T.bw - 2.0 > stop) break;
-    if (ring_covers_grid(T, bx0, by0, r)) break;
+      const BucketBox cb = bucket_box(T, cx0, cx1, cy0, cy1, 2.0 + rho * 1e-9);
+      bb.x0 = max(half.x0, cb.x0);
+      bb.x1 = min(half.x1, cb.x1);
+      bb.y0 = max(half.y0, cb.y0);
+      bb.y1 = min(half.y1, cb.y1);
+      rmax = max(max(bx0 - bb.x0, bb.x1 - bx0), max(by0 - bb.y0, bb.y1 - by0));
+    }
+  };
+  for (int r = 0; r <= rmax; ++r) {
+    const int ylo = by0 - r, yhi = by0 + r, xlo = bx0 - r, xhi = bx0 + r;
+    const BucketBox q = bb;
+    const int ya = max(ylo, q.y0), yb = min(yhi, q.y1);
+    for (int y = ya; y <= yb; ++y) {
+      if (y == ylo || y == yhi) {
+        const int xb = min(xhi, q.x1);
+        for (int x = max(xlo, q.x0); x <= xb; ++x) visit(x, y);
+      } else {
+        if (xlo >= q.x0 && xlo <= q.x1) visit(xlo, y);
+        if (r > 0 && xhi >= q.x0 && xhi <= q.x1) visit(xhi, y);
+      }
+    }
   }
   return best;
 }
@@ -424,6 +516,36 @@ __device__ __forceinline__ void texel_range(int lo, int hi, int H, int C, int R,
   if (j1 > R - 1) j1 = R - 1;
 }
 
+__device__ __forceinline__ bool tri_inside(int ax, int ay, int bx, int by, int cx, int cy, bool oa, bool ob, bool oc,
+                                           double qx, double qy) {
+  const double e0 = orient_d(bx, by, cx, cy, qx, qy);
+  if (e0 < 0.0 || (e0 == 0.0 && !oa)) return false;
+  const double e1 = orient_d(cx, cy, ax, ay, qx, qy);
+  if (e1 < 0.0 || (e1 == 0.0 && !ob)) return false;
+  const double e2 = orient_d(ax, ay, bx, by, qx, qy);
+  return !(e2 < 0.0 || (e2 == 0.0 && !oc));
+}
+
+// Narrow [lo, hi] to the x-interval of {q : orient(P, Q, q) >= 0} on the
+// horizontal line y = qy (approximate; the caller settles the ends exactly).
+__device__ __forceinline__ void edge_clip(int px, int py, int qx, int qy, double y, double& lo, double& hi) {
+  const double dy = qy - py;
+  const double k = (double)(qx - px) * (y - py);  // orient = k - dy * (x - px)
+  if (dy > 0.0)
+    hi = fmin(hi, px + k / dy);
+  else if (dy < 0.0)
+    lo = fmax(lo, px + k / dy);
+  else if (k < 0.0) {
+    lo = 1.0;
+    hi = 0.0;
+  }
+}
+
+// Write `key` into every texel whose centre lies in CCW triangle (a, b, c)
+// under the top-left rule.  Row by row: the span from the three edges is
+// widened by one texel, its two ends are settled with the exact test, and
+// the texels between them are filled without further tests (a triangle's
+// row section is an interval).
 __device__ void raster_triangle(const Tile& T, int a, int b, int c, int C, int R, uint64_t* __restrict__ fm) {
   const int2 A = T.uv[a], B = T.uv[b], Cc = T.uv[c];
   const int ax = A.x, ay = A.y, bx = B.x, by = B.y, cx = Cc.x, cy = Cc.y;
@@ -433,22 +555,26 @@ __device__ void raster_triangle(const Tile& T, int a, int b, int c, int C, int R
   const bool oa = edge_owned(bx, by, cx, cy), ob = edge_owned(cx, cy, ax, ay), oc = edge_owned(ax, ay, bx, by);
   const uint64_t key = face_key(a, b, c);
   const int q0 = -T.H + C / 2;
+  const double invC = 1.0 / C;
   for (int i = i0; i <= i1; ++i) {
     const double qy = q0 + i * C;
-    for (int j = j0; j <= j1; ++j) {
-      const double qx = q0 + j * C;
-      const double e0 = orient_d(bx, by, cx, cy, qx, qy);
-      if (e0 < 0.0 || (e0 == 0.0 && !oa)) continue;
-      const double e1 = orient_d(cx, cy, ax, ay, qx, qy);
-      if (e1 < 0.0 || (e1 == 0.0 && !ob)) continue;
-      const double e2 = orient_d(ax, ay, bx, by, qx, qy);
-      if (e2 < 0.0 || (e2 == 0.0 && !oc)) continue;
-      fm[i * R + j] = key;
-    }
+    double lo = -1e300, hi = 1e300;
+    edge_clip(bx, by, cx, cy, qy, lo, hi);
+    edge_clip(cx, cy, ax, ay, qy, lo, hi);
+    edge_clip(ax, ay, bx, by, qy, lo, hi);
+    if (!(lo <= hi + 2.0 * C)) continue;
+    int jl = max(j0, (int)floor((fmax(lo, -3.0 * T.H) - q0) * invC) - 1);
+    int jr = min(j1, (int)ceil((fmin(hi, 3.0 * T.H) - q0) * invC) + 1);
+    while (jl <= jr && !tri_inside(ax, ay, bx, by, cx, cy, oa, ob, oc, q0 + jl * C, qy)) ++jl;
+    while (jr >= jl && !tri_inside(ax, ay, bx, by, cx, cy, oa, ob, oc, q0 + jr * C, qy)) --jr;
+    uint64_t* __restrict__ row = fm + i * R;
+    for (int j = jl; j <= jr; ++j) row[j] = key;
   }
 }
 
-// Texels lying exactly on hull edge a->b get the triangle next to it.
+// Texels lying exactly on hull edge a->b get the triangle next to it.  Per
+// texel row the line crosses at most one texel centre, found exactly in
+// integers.
 __device__ void raster_hull_edge(const Tile& T, int a, int b, uint64_t key, int C, int R, uint64_t* __restrict__ fm) {
   const int2 A = T.uv[a], B = T.uv[b];
   const int ax = A.x, ay = A.y, bx = B.x, by = B.y;
@@ -456,9 +582,21 @@ __device__ void raster_hull_edge(const Tile& T, int a, int b, uint64_t key, int 
   texel_range(min(ax, bx), max(ax, bx), T.H, C, R, j0, j1);
   texel_range(min(ay, by), max(ay, by), T.H, C, R, i0, i1);
   const int q0 = -T.H + C / 2;
-  for (int i = i0; i <= i1; ++i)
-    for (int j = j0; j <= j1; ++j)
-      if (orient_d(ax, ay, bx, by, q0 + j * C, q0 + i * C) == 0.0) fm[i * R + j] = key;
+  const int64_t dx = bx - ax, dy = by - ay;
+  if (dy == 0) {
+    // the edge lies on a texel row only if ay is a row centre (then i0 == i1)
+    if (i0 > i1 || q0 + i0 * C != ay) return;
+    for (int j = j0; j <= j1; ++j) fm[i0 * R + j] = key;
+    return;
+  }
+  for (int i = i0; i <= i1; ++i) {
+    const int64_t num = dx * (int64_t)(q0 + i * C - ay);
+    if (num % dy) continue;
+    const int64_t x = ax + num / dy;
+    if ((x - q0) % C) continue;
+    const int64_t j = (x - q0) / C;
+    if (j >= j0 && j <= j1) fm[i * R + (int)j] = key;
+  }
 }
 
 __device__ int block_scan_excl(int* s, int n, int* s_tmp) {

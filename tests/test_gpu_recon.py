@@ -144,6 +144,41 @@ def test_planar_reproduction_lattice():
     assert gpu["status"][0] == 0
 
 
+def _window_points(u, v, rng):
+    z = rng.integers(0, 5000, len(u)).astype(np.int32)
+    rgb = rng.integers(0, 65536, (len(u), 3)).astype(np.uint16)
+    return ((np.asarray(u) + 32000).astype(np.int32), (np.asarray(v) + 32000).astype(np.int32), z, rgb)
+
+
+@pytest.mark.parametrize("n", [40, 900])
+def test_points_on_window_boundary_lines(n):
+    """Points on the four edges and corners of the window: hull edges lie on
+    the window boundary, where the neighbour search region is a thin strip."""
+    region = synth.Region()
+    rng = np.random.default_rng(n)
+    H = 48000
+    side = rng.integers(0, 5, n)
+    t, s = rng.integers(-H, H, n), rng.integers(-H, H, n)
+    u = np.select([side == 0, side == 1], [-H, H - 1], t)
+    v = np.select([side == 2, side == 3], [-H, H - 1], s)
+    u = np.concatenate([u, [-H, H - 1, -H, H - 1]])
+    v = np.concatenate([v, [-H, -H, H - 1, H - 1]])
+    _compare(region, _window_points(u, v, rng), np.zeros(1, np.int32))
+
+
+def test_near_collinear_band():
+    """Points in a narrow band along a line: circumcircles of neighbouring
+    triples are huge and the left-side caps thin."""
+    region = synth.Region()
+    rng = np.random.default_rng(3)
+    H = 48000
+    u = rng.integers(-H, H, 700)
+    v = np.clip((u * 3) // 7 + rng.integers(0, 3, 700), -H, H - 1)
+    extra_u, extra_v = rng.integers(-H, H, 30), rng.integers(-H, H, 30)
+    _compare(region, _window_points(np.concatenate([u, extra_u]), np.concatenate([v, extra_v]), rng),
+             np.zeros(1, np.int32))
+
+
 def test_deterministic_and_order_independent():
     w = synth.batch_tiles(seed=11, tiles_x=4, tiles_y=4)
     ps = w.points.numpy()
