@@ -247,7 +247,7 @@ def main():
         except Exception as e:  # secondary figure only
             out["splat"] = {"error": repr(e)}
         try:
-            out["backward"] = bench_backward(dev, w)
+            out["backward"] = bench_training(dev)
         except Exception as e:
             out["backward"] = {"error": repr(e)}
 
@@ -290,23 +290,86 @@ def bench_splat(n_points: int, dev):
             "frac_hbm_peak": alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
 
 
-def bench_backward(dev, w):
+def training_set(dev, dense_per_tile: int = 2_000_000, chunk_tiles: int = 16):
+    """256 tiles (16 x 16) with 200-800 sparse points each, reconstructed on
+    the GPU, and their targets: the max-height splat of `dense_per_tile`
+    dense points per tile of the same terrain (no noise), normalised."""
+    from paper_2509_20198_amd import train as T
+
     work = synth.train_tiles(seed=4, device=dev)
-    g = ls.Grid.of(work.region)
+    region = work.region
+    g = ls.Grid.of(region)
     ps = work.points
     tl = torch.from_numpy(work.tile_list).to(dev)
-    xo, cz, _ = ls.recon_tiles(g, ps.x, ps.y, ps.z, ps.rgb_u16(), tl)
-    nt = xo.shape[0]
-    gy = torch.randn((nt, 64, 64, 4), device=dev, generator=torch.Generator(device=dev).manual_seed(0))
-    act = torch.empty(ls.act_bytes(g, nt, ls.FP32), dtype=torch.uint8, device=dev)
-    ws = ls.alloc_workspace(ls.workspace_bytes(ls.OP_BACKWARD, g, nt, 0, ls.FP32), dev)
-    gw = torch.empty_like(w)
+    x, cz, _ = ls.recon_tiles(g, ps.x, ps.y, ps.z, ps.rgb_u16(), tl)
+    nt = len(work.tile_list)
+    ids = np.asarray(work.tile_list, np.int64)
+    slot = torch.full((region.tiles_x * region.tiles_y,), -1, dtype=torch.int32, device=dev)
+    slot[torch.from_numpy(ids).to(dev)] = torch.arange(nt, dtype=torch.int32, device=dev)
+    keys = torch.zeros((nt, region.res, region.res), dtype=torch.int64, device=dev)
+    nd = torch.zeros(1, dtype=torch.int64, device=dev)
+    for c in range(0, nt, chunk_tiles):
+        d = synth.fullres_points(region, ids[c:c + chunk_tiles], dense_per_tile, seed=1000 + c, noise_sigma_m=0.0,
+                                 device=dev, terrain_seed=4)
+        ls.splat_points(g, d.x, d.y, d.z, d.rgb_u16(), slot, nt, keys=keys, n_dropped=nd)
+        del d
+    tex = torch.zeros((nt, region.res, region.res, 4), dtype=torch.float32, device=dev)
+    ls.resolve_keys(g, keys, tex)
+    r_m = (region.tile_size / 2 + region.pad * region.cell) * region.scale_xy
+    t = T.normalise_target(tex, cz, r_m)
+    torch.cuda.synchronize()
+    return work, g, x, cz, t, int((keys == 0).sum().item())
 
-    def step():
-        ls.refine_tiles(w, xo, cz, g, ls.FP32, act_save=act, want_y=True, want_tex=False, ws=ws)
-        ls.refine_backward(w, xo, gy, g, ls.FP32, act_save=act, grad_w=gw, ws=ws)
-    ms = Timer().run(step, 3, 1)
-    return {"workload": f"{nt} tiles, FP32 forward + backward", "ms_per_step": ms, "tiles_per_s": nt / (ms * 1e-3)}
+
+def bench_training(dev, train_steps: int = 60):
+    """Refinement backward on the 256-tile training batch: FP32 and BF16
+    forward + backward step times (BF16 also with activation recomputation),
+    and a short AdamW run of the BF16 path from random weights."""
+    from paper_2509_20198_amd import train as T
+
+    t0 = time.perf_counter()
+    work, g, x, cz, t, empty = training_set(dev)
+    log(f"training set ready in {time.perf_counter() - t0:.1f} s")
+    nt = x.shape[0]
+    w0 = torch.from_numpy(synth.unet_weights(1).astype(np.float32)).to(dev)
+    gy = torch.randn((nt, g.res, g.res, 4), device=dev, generator=torch.Generator(device=dev).manual_seed(0))
+    out = {"workload": f"{nt} tiles (16 x 16), 200-800 sparse points per tile; targets from 2,000,000 dense "
+                       f"points per tile", "target_texels_without_points": empty}
+    for name, prec in (("fp32", ls.FP32), ("bf16", ls.BF16)):
+        wb = ls.pack_weights_bf16(w0) if prec == ls.BF16 else None
+        act = torch.empty(ls.act_bytes(g, nt, prec), dtype=torch.uint8, device=dev)
+        ws = ls.alloc_workspace(ls.workspace_bytes(ls.OP_BACKWARD, g, nt, 0, prec), dev)
+        gw = torch.empty_like(w0)
+
+        def step():
+            ls.refine_tiles(w0, x, cz, g, prec, w_bf16=wb, act_save=act, want_y=True, want_tex=False, ws=ws)
+            ls.refine_backward(w0, x, gy, g, prec, w_bf16=wb, act_save=act, grad_w=gw, ws=ws)
+
+        def step_recompute():
+            ls.refine_tiles(w0, x, cz, g, prec, w_bf16=wb, want_y=True, want_tex=False, ws=ws)
+            ls.refine_backward(w0, x, gy, g, prec, w_bf16=wb, grad_w=gw, ws=ws)
+
+        ms = Timer().run(step, 5, 2)
+        ms_rc = Timer().run(step_recompute, 5, 2)
+        out[name] = {"fwd_bwd_ms": ms, "tiles_per_s": nt / (ms * 1e-3), "fwd_bwd_recompute_ms": ms_rc,
+                     "saved_activation_bytes": int(act.numel())}
+        del act, ws
+    # training: BF16 convolutions, FP32 weights and optimiser state
+    base = float(T.l1_loss(T.linear_baseline(x, g.pad, g.res), t).item())
+    tr = T.Trainer(w0, g, ls.BF16, save_acts=True, total_steps=train_steps)
+    losses = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(train_steps):
+        losses.append(tr.step(x, t))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    losses = [float(v.item()) for v in losses]
+    out["train_bf16"] = {"steps": train_steps, "ms_per_step": dt / train_steps * 1e3,
+                         "tiles_per_s_trained": nt * train_steps / dt, "loss_first": losses[0],
+                         "loss_last": losses[-1], "loss_min": min(losses), "linear_baseline_loss": base,
+                         "optimizer": "AdamW lr 1e-4 betas (0.9, 0.999) eps 1e-5 wd 1e-2, x0.1 at 1/3 and 2/3"}
+    return out
 
 
 if __name__ == "__main__":

@@ -306,6 +306,37 @@ def refine_backward(w, x, grad_y, grid, precision: int = FP32, *, w_bf16=None, a
     return grad_w, grad_x
 
 
+class RefineFn(torch.autograd.Function):
+    """y = refine(x; w) as an autograd op over ls_refine_tiles / ls_refine_backward.
+
+    RefineFn.apply(x, w, grid, precision, save_acts) -> y [n, res, res, 4]
+    (normalised).  save_acts=False keeps no activations between forward and
+    backward: the backward recomputes the forward (activation recomputation,
+    for batches whose activations do not fit).  BF16 packs the weights on
+    every forward, so optimiser updates of w are seen."""
+
+    @staticmethod
+    def forward(ctx, x, w, grid, precision=FP32, save_acts=True):
+        g = Grid.of(grid)
+        x = x.contiguous()
+        wb = pack_weights_bf16(w) if precision == BF16 else None
+        act = None
+        if save_acts:
+            act = torch.empty(act_bytes(g, x.shape[0], precision), dtype=torch.uint8, device=x.device)
+        y, _ = refine_tiles(w, x, None, g, precision, w_bf16=wb, act_save=act, want_tex=False)
+        ctx.save_for_backward(x, w)
+        ctx.grid, ctx.precision, ctx.wb, ctx.act = g, precision, wb, act
+        return y
+
+    @staticmethod
+    def backward(ctx, grad_y):
+        x, w = ctx.saved_tensors
+        gw, gx = refine_backward(w, x, grad_y.contiguous(), ctx.grid, ctx.precision, w_bf16=ctx.wb,
+                                 act_save=ctx.act, want_grad_x=bool(ctx.needs_input_grad[0]))
+        ctx.act = None
+        return gx, gw, None, None, None
+
+
 def splat_points(grid, x, y, z, rgb, tile_slot, n_slots: int, keys=None, tex_inout=None, n_dropped=None,
                  stream=None):
     """Max-key splat of full-resolution points -> (keys [n_slots,res,res] int64 bits, n_dropped [1])."""

@@ -244,25 +244,13 @@ __device__ __forceinline__ double orient_d(double ax, double ay, double bx, doub
 
 __device__ __forceinline__ int sgn_d(double v) { return (v > 0.0) - (v < 0.0); }
 
-// Sign of the in-circle determinant of d against CCW (a, b, c): > 0 when d
-// is strictly inside.  Floating-point filter first, exact int128 otherwise,
-// then the symbolic perturbation for exactly cocircular points.
-__device__ int incircle_sos(const Tile& T, int a, int b, int c, int d, int2 pa, int2 pb, int2 pc, int2 pd) {
+// Exact sign of the in-circle determinant in int128 (|terms| < 2^72), then
+// the symbolic perturbation for exactly cocircular points.  Kept out of line:
+// the floating-point filter below settles nearly every call.
+__device__ __noinline__ int incircle_exact(int a, int b, int c, int d, int2 pa, int2 pb, int2 pc, int2 pd) {
   const int64_t adx = pa.x - pd.x, ady = pa.y - pd.y;
   const int64_t bdx = pb.x - pd.x, bdy = pb.y - pd.y;
   const int64_t cdx = pc.x - pd.x, cdy = pc.y - pd.y;
-  const double fadx = (double)adx, fady = (double)ady, fbdx = (double)bdx, fbdy = (double)bdy;
-  const double fcdx = (double)cdx, fcdy = (double)cdy;
-  const double al = fadx * fadx + fady * fady;
-  const double bl = fbdx * fbdx + fbdy * fbdy;
-  const double cl = fcdx * fcdx + fcdy * fcdy;
-  const double bc = fbdx * fcdy - fcdx * fbdy;
-  const double ca = fcdx * fady - fadx * fcdy;
-  const double ab = fadx * fbdy - fbdx * fady;
-  const double t1 = al * bc, t2 = bl * ca, t3 = cl * ab;
-  const double det = t1 + t2 + t3;
-  const double perm = fabs(t1) + fabs(t2) + fabs(t3);
-  if (fabs(det) > 8.8817841970012523e-16 * perm) return sgn_d(det);  // 8 * 2^-53
   const __int128 e = (__int128)(adx * adx + ady * ady) * (__int128)(bdx * cdy - cdx * bdy) +
                      (__int128)(bdx * bdx + bdy * bdy) * (__int128)(cdx * ady - adx * cdy) +
                      (__int128)(cdx * cdx + cdy * cdy) * (__int128)(adx * bdy - bdx * ady);
@@ -276,6 +264,26 @@ __device__ int incircle_sos(const Tile& T, int a, int b, int c, int d, int2 pa, 
   if (w == a) return sgn_d(orient_d(pb.x, pb.y, pc.x, pc.y, pd.x, pd.y));
   if (w == b) return sgn_d(orient_d(pc.x, pc.y, pa.x, pa.y, pd.x, pd.y));
   return sgn_d(orient_d(pa.x, pa.y, pb.x, pb.y, pd.x, pd.y));
+}
+
+// Sign of the in-circle determinant of d against CCW (a, b, c): > 0 when d
+// is strictly inside.  Floating-point filter first, exact int128 otherwise,
+// then the symbolic perturbation for exactly cocircular points.
+__device__ __forceinline__ int incircle_sos(int a, int b, int c, int d, int2 pa, int2 pb, int2 pc, int2 pd) {
+  const double fadx = (double)(pa.x - pd.x), fady = (double)(pa.y - pd.y);
+  const double fbdx = (double)(pb.x - pd.x), fbdy = (double)(pb.y - pd.y);
+  const double fcdx = (double)(pc.x - pd.x), fcdy = (double)(pc.y - pd.y);
+  const double al = fadx * fadx + fady * fady;
+  const double bl = fbdx * fbdx + fbdy * fbdy;
+  const double cl = fcdx * fcdx + fcdy * fcdy;
+  const double bc = fbdx * fcdy - fcdx * fbdy;
+  const double ca = fcdx * fady - fadx * fcdy;
+  const double ab = fadx * fbdy - fbdx * fady;
+  const double t1 = al * bc, t2 = bl * ca, t3 = cl * ab;
+  const double det = t1 + t2 + t3;
+  const double perm = fabs(t1) + fabs(t2) + fabs(t3);
+  if (fabs(det) > 8.8817841970012523e-16 * perm) return sgn_d(det);  // 8 * 2^-53
+  return incircle_exact(a, b, c, d, pa, pb, pc, pd);
 }
 
 __device__ __forceinline__ bool ring_covers_grid(const Tile& T, int bx0, int by0, int r) {
@@ -424,7 +432,7 @@ __device__ int third_left(const Tile& T, int a, int b) {
       if (p == a || p == b) continue;
       const int2 P = T.uv[p];
       if (orient_d(ax, ay, bx, by, P.x, P.y) <= 0.0) continue;
-      if (best >= 0 && incircle_sos(T, a, b, best, p, A, B, C, P) <= 0) continue;
+      if (best >= 0 && incircle_sos(a, b, best, p, A, B, C, P) <= 0) continue;
       best = p;
       C = P;
       // circumcircle of (a, b, p) relative to a
@@ -462,17 +470,34 @@ __device__ int third_left(const Tile& T, int a, int b) {
     }
   };
   for (int r = 0; r <= rmax; ++r) {
-    const int ylo = by0 - r, yhi = by0 + r, xlo = bx0 - r, xhi = bx0 + r;
+    // the cells of ring r inside the box, enumerated by one index so the
+    // bucket visit is instantiated once: bottom row, side cells of the
+    // middle rows, top row
     const BucketBox q = bb;
-    const int ya = max(ylo, q.y0), yb = min(yhi, q.y1);
-    for (int y = ya; y <= yb; ++y) {
-      if (y == ylo || y == yhi) {
-        const int xb = min(xhi, q.x1);
-        for (int x = max(xlo, q.x0); x <= xb; ++x) visit(x, y);
+    const int ylo = by0 - r, yhi = by0 + r, xlo = bx0 - r, xhi = bx0 + r;
+    const int X0 = max(xlo, q.x0), X1 = min(xhi, q.x1);
+    const int nrow = X1 >= X0 ? X1 - X0 + 1 : 0;
+    const int nA = (ylo >= q.y0 && ylo <= q.y1) ? nrow : 0;
+    const int nC = (r > 0 && yhi >= q.y0 && yhi <= q.y1) ? nrow : 0;
+    const int ym0 = max(ylo + 1, q.y0), ym1 = min(yhi - 1, q.y1);
+    const bool sL = xlo >= q.x0 && xlo <= q.x1, sR = xhi >= q.x0 && xhi <= q.x1;
+    const int k = (int)sL + (int)sR;
+    const int nB = ym1 >= ym0 ? (ym1 - ym0 + 1) * k : 0;
+    const int total = nA + nB + nC;
+    for (int t = 0; t < total; ++t) {
+      int cx, cy;
+      if (t < nA) {
+        cy = ylo;
+        cx = X0 + t;
+      } else if (t < nA + nB) {
+        const int u = t - nA;
+        cy = ym0 + (k == 2 ? (u >> 1) : u);
+        cx = (k == 2) ? ((u & 1) ? xhi : xlo) : (sL ? xlo : xhi);
       } else {
-        if (xlo >= q.x0 && xlo <= q.x1) visit(xlo, y);
-        if (r > 0 && xhi >= q.x0 && xhi <= q.x1) visit(xhi, y);
+        cy = yhi;
+        cx = X0 + (t - nA - nB);
       }
+      visit(cx, cy);
     }
   }
   return best;
@@ -650,7 +675,10 @@ __device__ __forceinline__ void write_zero_tile(const ReconParams& P, int k) {
   for (int64_t i = threadIdx.x; i < n8; i += RB) o[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-__global__ void __launch_bounds__(RB) k_recon(ReconParams P) {
+// Four waves per SIMD (128 VGPRs) so two 512-lane workgroups share a CU: the
+// searches are latency-bound (LDS reads, dependent FP64 chains), and the
+// second workgroup hides more of it than the few spills this costs.
+__global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
   // region 0 holds the raw bucket offsets while bucketing, then the
   // canonical coordinates; the canonical bucket offsets sit at the end
   __shared__ int s_mem[LDS_INTS];

@@ -43,6 +43,10 @@ struct RefineWs {
   // backward
   float *dXC, *dA10, *dA9, *dU1, *dA8, *dA2, *dA7, *dU2, *dA6, *dA4, *dA5, *dP2, *dA3, *dP1, *dA1;
   float* partial;
+  // BF16 backward: turned weights, masked BF16 gradient, padded head gradient
+  uint16_t* wdb;
+  uint16_t* gz;
+  uint16_t* gy8;
 };
 
 size_t refine_layout(const LsGridInfo& gi, int32_t B, int precision, int backward, bool need_acts, void* base,
@@ -74,6 +78,11 @@ size_t refine_layout(const LsGridInfo& gi, int32_t B, int precision, int backwar
     W->dP1 = A.take<float>(B * 16 * h);
     W->dA1 = A.take<float>(B * 16 * f);
     W->partial = A.take<float>(WG_MAX_CHUNKS * MAX_LAYER_PARAMS);
+    if (precision == LS_BF16) {
+      W->wdb = A.take<uint16_t>(ls_bf16_dpacked_total());
+      W->gz = A.take<uint16_t>(B * 16 * f);
+      W->gy8 = A.take<uint16_t>((int64_t)B * res * res * 8);
+    }
   }
   return A.used;
 }
@@ -166,11 +175,48 @@ int wgrad(const ConvSrc& s, int B, int H, int l, const float* dA, const float* m
   a.cout = LS_LAYERS[l].cout;
   a.dA = dA;
   a.mask = mask;
+  a.g_bf16 = nullptr;
   a.d_stride = d_stride;
+  a.round_in = 0;
   a.partial = partial;
   const int64_t npix = (int64_t)B * Ho * Wo;
   a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(WG_MAX_CHUNKS, npix / 256));
   return ls_wgrad_f32(a, grad_w + ls_layer_w_offset(l), st);
+}
+
+// BF16 path: the gradient is the pre-masked BF16 tensor g (d_stride
+// channels per pixel); FP32-stored inputs are rounded to BF16 on load.
+int wgrad_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* g, int d_stride, int y0, int x0, int Ho, int Wo,
+               float* grad_w, float* partial, hipStream_t st) {
+  WgradArgs a;
+  a.src = s;
+  a.B = B;
+  a.H = H;
+  a.W = H;
+  a.y0 = y0;
+  a.x0 = x0;
+  a.Ho = Ho;
+  a.Wo = Wo;
+  a.cout = LS_LAYERS[l].cout;
+  a.dA = nullptr;
+  a.mask = nullptr;
+  a.g_bf16 = g;
+  a.d_stride = d_stride;
+  a.round_in = 1;
+  a.partial = partial;
+  const int64_t npix = (int64_t)B * Ho * Wo;
+  a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(WG_MAX_CHUNKS, npix / 256));
+  return ls_wgrad_f32(a, grad_w + ls_layer_w_offset(l), st);
+}
+
+SrcPart bsrc(const uint16_t* p, int c, int hw) {
+  SrcPart s = src_none();
+  s.bf16 = p;
+  s.c = c;
+  s.h = hw;
+  s.w = hw;
+  s.stride = c;
+  return s;
 }
 
 // dgrad of layer l: out = conv(dA masked by A, flipped/transposed weights)
@@ -268,6 +314,69 @@ int backward_f32(const float* w, const float* wd, const float* x, const float* a
   return LS_OK;
 }
 
+// BF16 backward: activations saved in BF16, every conv product (dgrad on
+// the matrix cores, wgrad on the vector units) takes BF16 operands with FP32
+// accumulation; gradients between layers stay FP32 and are rounded to BF16
+// (after the ReLU mask) only as conv operands.
+int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int B, const LsGridInfo& gi,
+                  float* grad_w, float* grad_x, const RefineWs& W, hipStream_t st) {
+  const int R = gi.R, R2 = R / 2, R4 = R / 4, res = gi.res, pad = gi.pad;
+  const int64_t f = (int64_t)R * R, h = f / 4, q = f / 16;
+  const Acts al = act_layout(R);
+  auto A = [&](int i) { return acts + al.off[i] * B; };
+  auto P = [&](int i, int c, int hw) { return bsrc(A(i), c, hw); };
+  const SrcPart X = src_plain(x, 8, R, R, 8, 0, nullptr);
+  // mask + round the gradient of layer l's output, then its wgrad and dgrad
+  auto layer = [&](int l, const float* dA, int act, const ConvSrc& in, int H, float* dX) -> int {
+    const int cout = LS_LAYERS[l].cout;
+    LS_TRY(ls_bf16_mask_round(dA, A(act), W.gz, (int64_t)B * H * H * cout, st));
+    LS_TRY(wgrad_bf16(in, B, H, l, W.gz, cout, 0, 0, H, H, grad_w, W.partial, st));
+    if (!dX) return LS_OK;
+    return ls_bf16_dgrad(one(bsrc(W.gz, cout, H)), B, H, l, W.wdb, dX, st);
+  };
+  // head: gradient embedded at the crop, padded to 8 channels
+  LS_TRY(ls_bf16_embed8(grad_y, W.gy8, (int64_t)B * res * res, st));
+  {
+    SrcPart g = bsrc(W.gy8, 8, res);
+    g.oy = pad;
+    g.ox = pad;
+    LS_TRY(ls_bf16_dgrad(one(g), B, R, HEAD, W.wdb, W.dXC, st));
+  }
+  LS_TRY(wgrad_bf16(two(P(iA10, 16, R), X), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
+  LS_TRY(ls_copy_channels(W.dXC, 24, 0, W.dA10, 16, B * f, 0, st));
+  // decoder level 1
+  LS_TRY(layer(D1B, W.dA10, iA10, one(P(iA9, 16, R)), R, W.dA9));
+  SrcPart u8 = P(iA8, 32, R2);
+  u8.up = 1;
+  LS_TRY(layer(D1A, W.dA9, iA9, two(u8, P(iA2, 16, R)), R, W.dU1));
+  LS_TRY(ls_up_adjoint(W.dU1, 48, W.dA8, B, R2, R2, 32, st));
+  LS_TRY(ls_copy_channels(W.dU1, 48, 32, W.dA2, 16, B * f, 0, st));
+  // decoder level 2
+  LS_TRY(layer(D2B, W.dA8, iA8, one(P(iA7, 32, R2)), R2, W.dA7));
+  SrcPart u6 = P(iA6, 64, R4);
+  u6.up = 1;
+  LS_TRY(layer(D2A, W.dA7, iA7, two(u6, P(iA4, 32, R2)), R2, W.dU2));
+  LS_TRY(ls_up_adjoint(W.dU2, 96, W.dA6, B, R4, R4, 64, st));
+  LS_TRY(ls_copy_channels(W.dU2, 96, 64, W.dA4, 32, B * h, 0, st));
+  // bottleneck
+  LS_TRY(layer(BB, W.dA6, iA6, one(P(iA5, 64, R4)), R4, W.dA5));
+  LS_TRY(layer(BA, W.dA5, iA5, one(P(iP2, 32, R4)), R4, W.dP2));
+  LS_TRY(ls_pool_adjoint_add(W.dP2, W.dA4, B, R2, R2, 32, st));
+  // encoder level 2
+  LS_TRY(layer(E2B, W.dA4, iA4, one(P(iA3, 32, R2)), R2, W.dA3));
+  LS_TRY(layer(E2A, W.dA3, iA3, one(P(iP1, 16, R2)), R2, W.dP1));
+  LS_TRY(ls_pool_adjoint_add(W.dP1, W.dA2, B, R, R, 16, st));
+  // encoder level 1
+  LS_TRY(layer(E1B, W.dA2, iA2, one(P(iA1, 16, R)), R, W.dA1));
+  LS_TRY(layer(E1A, W.dA1, iA1, one(X), R, grad_x));
+  if (grad_x) {
+    LS_TRY(ls_copy_channels(W.dXC, 24, 16, grad_x, 8, B * f, 1, st));
+    LS_TRY(ls_residual_adjoint(grad_y, grad_x, B, res, pad, st));
+  }
+  (void)q;
+  return LS_OK;
+}
+
 }  // namespace
 
 size_t ls_refine_act_bytes(const LsGridInfo& gi, int32_t n_tiles, int precision) {
@@ -316,5 +425,12 @@ int ls_refine_backward_impl(const float* w, const uint16_t* w_bf16, int precisio
     }
     return backward_f32(w, W.wd, x, acts, grad_y, n_tiles, gi, grad_w, grad_x, W, st);
   }
-  return LS_ENOTIMPL;
+  LS_TRY(ls_bf16_prep_weights(w_bf16, W.wbt, st));
+  LS_TRY(ls_bf16_prep_dgrad_weights(w_bf16, W.wdb, st));
+  const uint16_t* acts = reinterpret_cast<const uint16_t*>(act_save);
+  if (!acts) {
+    LS_TRY(ls_bf16_forward(w, W.wbt, x, n_tiles, gi, reinterpret_cast<uint16_t*>(W.acts), W.head, st));
+    acts = reinterpret_cast<const uint16_t*>(W.acts);
+  }
+  return backward_bf16(x, acts, grad_y, n_tiles, gi, grad_w, grad_x, W, st);
 }

@@ -7,11 +7,13 @@
 // The maximum is commutative, so the result is bit-exact for any order.
 //
 // k_splat: a workgroup takes a batch of SPLAT_BATCH consecutive points
-// (coalesced SoA loads).  When the batch's texels fall in a short range of
-// Morton codes (the case for Morton-ordered full-resolution chunks), the
-// batch is first reduced in LDS with 64-bit max (one slot per Morton code)
-// and then flushed with one global 64-bit atomic max per touched texel;
-// otherwise every point goes straight to a global atomic max.
+// (coalesced, non-temporal SoA quad loads).  When the batch's texels fall in
+// a short range of Morton codes (the case for Morton-ordered full-resolution
+// chunks), the batch is first reduced in LDS with 64-bit max (one slot per
+// Morton code) and then flushed with one global 64-bit atomic max per
+// touched texel; otherwise every point goes straight to a global atomic max.
+// The small window (16 KB) lets eight workgroups share a CU, so the loads of
+// some overlap the LDS phases of others.
 #include <algorithm>
 
 #include "ls_common.hpp"
@@ -19,19 +21,49 @@
 namespace {
 
 constexpr int SPLAT_THREADS = 256;
-constexpr int SPLAT_PAIRS = 8;                                   // point pairs per thread per batch
-constexpr int SPLAT_PPT = 2 * SPLAT_PAIRS;                       // points per thread per batch
-constexpr int SPLAT_BATCH = SPLAT_THREADS * SPLAT_PPT;           // points per batch
-constexpr int SPLAT_WIN = 8192;                                  // LDS window (64 KB of keys)
+#ifndef LS_SPLAT_PPT
+#define LS_SPLAT_PPT 8
+#endif
+#ifndef LS_SPLAT_WIN
+#define LS_SPLAT_WIN 2048
+#endif
+constexpr int SPLAT_PPT = LS_SPLAT_PPT;                 // points per thread per batch (multiple of 4)
+constexpr int SPLAT_QPT = SPLAT_PPT / 4;                // point quads per thread per batch
+constexpr int SPLAT_BATCH = SPLAT_THREADS * SPLAT_PPT;  // points per batch
+constexpr int SPLAT_WIN = LS_SPLAT_WIN;                 // LDS window of 64-bit keys
+static_assert(SPLAT_PPT % 4 == 0, "points are loaded in quads");
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+
+// floor(n / d) for 0 <= n < 2^31 as a multiply-high and shift (Granlund and
+// Montgomery, 1994): with l = ceil(log2 d) and m = ceil(2^(31+l) / d) < 2^32,
+// floor(n / d) = floor(n * m / 2^(31+l)) exactly over that range.
+struct MagicDiv {
+  uint32_t m;
+  int s;  // 31 + l
+  __device__ __forceinline__ int operator()(int64_t n) const {
+    return (int)(((uint64_t)(uint32_t)n * m) >> s);
+  }
+};
+
+static MagicDiv magic_div(uint32_t d) {
+  int l = 0;
+  while ((1ull << l) < d) ++l;
+  MagicDiv r;
+  r.m = (uint32_t)(((1ull << (31 + l)) + d - 1) / d);
+  r.s = 31 + l;
+  return r;
+}
 
 struct SplatParams {
   int64_t ox, oy;
   int32_t C, res, tiles_x, tiles_y;
-  double inv_C, inv_res;
+  MagicDiv divC, divR;
   int32_t gw, gh;  // global texel extent
   int32_t n_slots;
   int32_t morton_ok;
-  int32_t vec_ok;  // x, y, z 8-byte aligned and rgb 4-byte aligned: pairwise vector loads
+  int32_t vec_ok;  // x, y, z 16-byte and rgb 8-byte aligned: quad vector loads
   int64_t n;
   const int32_t* x;
   const int32_t* y;
@@ -60,18 +92,9 @@ __device__ __forceinline__ uint32_t compact16(uint32_t v) {
   return v;
 }
 
-// floor(a / b) for 0 <= a < 2^31, b > 0, from a double reciprocal plus a
-// one-step correction (the product is within one of the quotient)
-__device__ __forceinline__ int udiv(int64_t a, int b, double inv) {
-  int q = (int)((double)a * inv);
-  if ((int64_t)q * b > a) --q;
-  else if ((int64_t)(q + 1) * b <= a) ++q;
-  return q;
-}
-
 // texel index of (gx, gy) in the key array; the tile must be mapped
 __device__ __forceinline__ int64_t cell_of(const SplatParams& p, int gx, int gy) {
-  const int tx = udiv(gx, p.res, p.inv_res), ty = udiv(gy, p.res, p.inv_res);
+  const int tx = p.divR(gx), ty = p.divR(gy);
   const int s = p.tile_slot[ty * p.tiles_x + tx];
   return ((int64_t)s * p.res + (gy - ty * p.res)) * p.res + (gx - tx * p.res);
 }
@@ -83,9 +106,9 @@ __device__ __forceinline__ bool point_key(const SplatParams& p, int xi, int yi, 
   const int64_t dx = (int64_t)xi - p.ox, dy = (int64_t)yi - p.oy;
   if (dx < 0 || dy < 0) return false;
   if (dx >= (int64_t)p.gw * p.C || dy >= (int64_t)p.gh * p.C) return false;
-  gx = udiv(dx, p.C, p.inv_C);
-  gy = udiv(dy, p.C, p.inv_C);
-  const int tx = udiv(gx, p.res, p.inv_res), ty = udiv(gy, p.res, p.inv_res);
+  gx = p.divC(dx);
+  gy = p.divC(dy);
+  const int tx = p.divR(gx), ty = p.divR(gy);
   const int32_t s = p.tile_slot[ty * p.tiles_x + tx];
   if (s < 0 || s >= p.n_slots) return false;
   const uint32_t zz = (uint32_t)zi ^ 0x80000000u;
@@ -94,72 +117,119 @@ __device__ __forceinline__ bool point_key(const SplatParams& p, int xi, int yi, 
   return true;
 }
 
+// Raw fields of the SPLAT_PPT points a thread owns in one batch.
+struct SplatRegs {
+  int x[SPLAT_PPT], y[SPLAT_PPT], z[SPLAT_PPT];
+  uint32_t c[SPLAT_PPT * 3 / 2];  // 16-bit colours of each quad, two per dword, in input order
+  uint32_t valid;                 // bit s: point s exists (ragged last batch)
+};
+
+// Thread t owns the quads base/4 + k*SPLAT_THREADS + t (k < SPLAT_QPT).  The
+// points are streamed once: non-temporal loads keep the key array resident
+// in the caches instead.
+__device__ __forceinline__ void splat_load(const SplatParams& p, int64_t base, int tid, SplatRegs& r) {
+  const int64_t q0 = base / 4 + tid;
+  if (p.vec_ok && base + SPLAT_BATCH <= p.n) {
+#pragma unroll
+    for (int k = 0; k < SPLAT_QPT; ++k) {
+      const int64_t q = q0 + (int64_t)k * SPLAT_THREADS;
+      const v4i xv = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(p.x) + q);
+      const v4i yv = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(p.y) + q);
+      const v4i zv = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(p.z) + q);
+      const v2u* cp = reinterpret_cast<const v2u*>(p.rgb) + 3 * q;
+      const v2u c0 = __builtin_nontemporal_load(cp), c1 = __builtin_nontemporal_load(cp + 1),
+                c2 = __builtin_nontemporal_load(cp + 2);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        r.x[4 * k + e] = xv[e];
+        r.y[4 * k + e] = yv[e];
+        r.z[4 * k + e] = zv[e];
+      }
+      r.c[6 * k + 0] = c0.x;
+      r.c[6 * k + 1] = c0.y;
+      r.c[6 * k + 2] = c1.x;
+      r.c[6 * k + 3] = c1.y;
+      r.c[6 * k + 4] = c2.x;
+      r.c[6 * k + 5] = c2.y;
+    }
+    r.valid = (SPLAT_PPT == 32) ? 0xFFFFFFFFu : ((1u << SPLAT_PPT) - 1u);
+    return;
+  }
+  // ragged or unaligned batch: point by point, bounds-checked
+  r.valid = 0;
+#pragma unroll
+  for (int k = 0; k < SPLAT_QPT; ++k) {
+#pragma unroll
+    for (int w = 0; w < 6; ++w) r.c[6 * k + w] = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = 4 * (q0 + (int64_t)k * SPLAT_THREADS) + e;
+      const int s = 4 * k + e;
+      r.x[s] = r.y[s] = r.z[s] = 0;
+      if (i >= p.n) continue;
+      r.valid |= 1u << s;
+      r.x[s] = p.x[i];
+      r.y[s] = p.y[i];
+      r.z[s] = p.z[i];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const int v = 3 * e + ch;  // colour value index within the quad
+        r.c[6 * k + v / 2] |= (uint32_t)p.rgb[3 * i + ch] << (16 * (v & 1));
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t splat_colour(const SplatRegs& r, int s, int ch) {
+  const int k = s >> 2, v = 3 * (s & 3) + ch;
+  const uint32_t w = r.c[6 * k + v / 2];
+  return (v & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+// One workgroup per batch of SPLAT_BATCH consecutive points (grid-stride).
+// When the batch's texels span fewer than SPLAT_WIN Morton codes, keys are
+// first max-reduced in an LDS window indexed by Morton code and flushed with
+// one global 64-bit atomic max per touched texel; otherwise every point
+// goes straight to a global atomic max.
 __global__ void __launch_bounds__(SPLAT_THREADS) k_splat(SplatParams p) {
   __shared__ unsigned long long s_win[SPLAT_WIN];
   __shared__ uint32_t s_lo[SPLAT_THREADS / 64], s_hi[SPLAT_THREADS / 64];
   __shared__ unsigned long long s_drop[SPLAT_THREADS / 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   unsigned long long dropped = 0;
+  // invariant: the window is all zero when a batch starts (the flush clears
+  // the slots it reads)
+  for (int w = tid; w < SPLAT_WIN; w += SPLAT_THREADS) s_win[w] = 0;
   for (int64_t base = (int64_t)blockIdx.x * SPLAT_BATCH; base < p.n; base += (int64_t)gridDim.x * SPLAT_BATCH) {
+    SplatRegs r;
+    splat_load(p, base, tid, r);
     unsigned long long key[SPLAT_PPT];
     int gxs[SPLAT_PPT], gys[SPLAT_PPT];
     uint32_t lo = 0xFFFFFFFFu, hi = 0;
-    const int64_t pbase = base >> 1;
 #pragma unroll
-    for (int k = 0; k < SPLAT_PAIRS; ++k) {
-      const int64_t pr = pbase + (int64_t)k * SPLAT_THREADS + tid;
-      const int64_t i0 = 2 * pr;
-      int xv[2], yv[2], zv[2];
-      uint32_t rv[2], gv[2], bv[2];
-      int nv = 0;
-      if (p.vec_ok && i0 + 1 < p.n) {
-        const int2 x2 = reinterpret_cast<const int2*>(p.x)[pr];
-        const int2 y2 = reinterpret_cast<const int2*>(p.y)[pr];
-        const int2 z2 = reinterpret_cast<const int2*>(p.z)[pr];
-        const uint32_t* c = reinterpret_cast<const uint32_t*>(p.rgb) + 3 * pr;
-        const uint32_t c0 = c[0], c1 = c[1], c2 = c[2];
-        xv[0] = x2.x; xv[1] = x2.y;
-        yv[0] = y2.x; yv[1] = y2.y;
-        zv[0] = z2.x; zv[1] = z2.y;
-        rv[0] = c0 & 0xFFFF; gv[0] = c0 >> 16; bv[0] = c1 & 0xFFFF;
-        rv[1] = c1 >> 16; gv[1] = c2 & 0xFFFF; bv[1] = c2 >> 16;
-        nv = 2;
-      } else {
-        for (int q = 0; q < 2; ++q) {
-          const int64_t i = i0 + q;
-          if (i >= p.n) break;
-          xv[q] = p.x[i];
-          yv[q] = p.y[i];
-          zv[q] = p.z[i];
-          rv[q] = p.rgb[3 * i];
-          gv[q] = p.rgb[3 * i + 1];
-          bv[q] = p.rgb[3 * i + 2];
-          nv = q + 1;
-        }
+    for (int s = 0; s < SPLAT_PPT; ++s) {
+      key[s] = 0;
+      gxs[s] = gys[s] = 0;
+      if (!((r.valid >> s) & 1u)) continue;
+      int gx, gy;
+      unsigned long long kk;
+      if (!point_key(p, r.x[s], r.y[s], r.z[s], splat_colour(r, s, 0), splat_colour(r, s, 1), splat_colour(r, s, 2),
+                     kk, gx, gy)) {
+        ++dropped;
+        continue;
       }
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int slot = 2 * k + q;
-        key[slot] = 0;
-        if (q >= nv) continue;
-        int gx, gy;
-        if (!point_key(p, xv[q], yv[q], zv[q], rv[q], gv[q], bv[q], key[slot], gx, gy)) {
-          key[slot] = 0;
-          ++dropped;
-          continue;
-        }
-        gxs[slot] = gx;
-        gys[slot] = gy;
-        if (p.morton_ok) {
-          const uint32_t mc = spread16((uint32_t)gx) | (spread16((uint32_t)gy) << 1);
-          lo = min(lo, mc);
-          hi = max(hi, mc);
-        }
+      key[s] = kk;
+      gxs[s] = gx;
+      gys[s] = gy;
+      if (p.morton_ok) {
+        const uint32_t mc = spread16((uint32_t)gx) | (spread16((uint32_t)gy) << 1);
+        lo = min(lo, mc);
+        hi = max(hi, mc);
       }
     }
     bool use_lds = false;
     if (p.morton_ok) {
-      // block min / max of the Morton codes: wave shuffles, then 4 values
+      // block min / max of the Morton codes: wave shuffles, then one value per wave
       for (int o = 32; o > 0; o >>= 1) {
         lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
         hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
@@ -175,35 +245,35 @@ __global__ void __launch_bounds__(SPLAT_THREADS) k_splat(SplatParams p) {
         blo = min(blo, s_lo[w]);
         bhi = max(bhi, s_hi[w]);
       }
-      // uniform by construction; readfirstlane lets the compiler keep the
-      // barriers below in uniform control flow
+      // uniform by construction; readfirstlane keeps the barriers below in
+      // provably uniform control flow
       blo = (uint32_t)__builtin_amdgcn_readfirstlane((int)blo);
       bhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)bhi);
       use_lds = bhi >= blo && (bhi - blo) < (uint32_t)SPLAT_WIN;
       if (use_lds) {
-        const int span = (int)(bhi - blo) + 1;
-        for (int w = tid; w < span; w += SPLAT_THREADS) s_win[w] = 0;
-        __syncthreads();
 #pragma unroll
-        for (int k = 0; k < SPLAT_PPT; ++k)
-          if (key[k]) {
-            const uint32_t mc = spread16((uint32_t)gxs[k]) | (spread16((uint32_t)gys[k]) << 1);
-            atomicMax(&s_win[mc - blo], key[k]);
+        for (int s = 0; s < SPLAT_PPT; ++s)
+          if (key[s]) {
+            const uint32_t mc = spread16((uint32_t)gxs[s]) | (spread16((uint32_t)gys[s]) << 1);
+            atomicMax(&s_win[mc - blo], key[s]);
           }
         __syncthreads();
+        const int span = (int)(bhi - blo) + 1;
         for (int w = tid; w < span; w += SPLAT_THREADS) {
           const unsigned long long kv = s_win[w];
           if (!kv) continue;
+          s_win[w] = 0;
           const uint32_t code = blo + (uint32_t)w;
           atomicMax(&p.keys[cell_of(p, (int)compact16(code), (int)compact16(code >> 1))], kv);
         }
+        // the next batch's first barrier (or the kernel's end) orders these
+        // clears before the window is used again
       }
-      __syncthreads();
     }
     if (!use_lds) {
 #pragma unroll
-      for (int k = 0; k < SPLAT_PPT; ++k)
-        if (key[k]) atomicMax(&p.keys[cell_of(p, gxs[k], gys[k])], key[k]);
+      for (int s = 0; s < SPLAT_PPT; ++s)
+        if (key[s]) atomicMax(&p.keys[cell_of(p, gxs[s], gys[s])], key[s]);
     }
   }
   // one global atomic per workgroup for the dropped count
@@ -267,8 +337,8 @@ int ls_splat_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   p.oy = gi.oy;
   p.C = gi.C;
   p.res = gi.res;
-  p.inv_C = 1.0 / gi.C;
-  p.inv_res = 1.0 / gi.res;
+  p.divC = magic_div((uint32_t)gi.C);
+  p.divR = magic_div((uint32_t)gi.res);
   p.tiles_x = gi.tx;
   p.tiles_y = gi.ty;
   const int64_t gw = (int64_t)gi.tx * gi.res, gh = (int64_t)gi.ty * gi.res;
@@ -278,7 +348,7 @@ int ls_splat_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   p.n_slots = n_slots;
   p.morton_ok = (gw <= 65536 && gh <= 65536) ? 1 : 0;
   auto al = [](const void* q, uintptr_t a) { return (reinterpret_cast<uintptr_t>(q) % a) == 0; };
-  p.vec_ok = (al(x, 8) && al(y, 8) && al(z, 8) && al(rgb, 4)) ? 1 : 0;
+  p.vec_ok = (al(x, 16) && al(y, 16) && al(z, 16) && al(rgb, 8)) ? 1 : 0;
   p.n = n;
   p.x = x;
   p.y = y;

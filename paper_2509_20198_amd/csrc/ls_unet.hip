@@ -160,53 +160,137 @@ __global__ void k_head_epilogue(const float* __restrict__ head, const float* __r
 }
 
 // ---------------------------------------------------------------- backward
-// dW partials: thread per (weight | bias) element, blockIdx.y = pixel chunk.
-// dZ(p, co) = dA[p][co] * (A[p][co] > 0) (mask optional), defined on the
-// output window; the input is read through the forward ConvSrc.
-__global__ void __launch_bounds__(CT) k_wgrad_f32(WgradArgs A) {
+// dW partials as a register-tiled product: dW[co][n] = sum over pixels of
+// dZ(p, co) * I(p, n), with n = tap*cin + ci the im2col column and column
+// n = 9*cin standing for the bias (I = 1).  dZ(p, co) = dA[p][co] masked by
+// A[p][co] > 0 (or a pre-masked BF16 copy), defined on the output window;
+// I is read through the forward ConvSrc.  A workgroup owns one pixel chunk
+// (blockIdx.y) and WG_COLS columns (blockIdx.x) for all output channels;
+// slabs of WG_KP pixels are staged in LDS and every thread accumulates a
+// 4x4 block (4 channels x 4 columns) in FP32, in a fixed order.
+constexpr int WG_KP = 32;
+
+__device__ __forceinline__ float bf16_round(float f) {
+  return __builtin_bit_cast(float, (uint32_t)__builtin_bit_cast(unsigned short, static_cast<__bf16>(f)) << 16);
+}
+
+__device__ __forceinline__ float4 bf16x4_to_f32(uint2 v) {
+  return make_float4(__builtin_bit_cast(float, v.x << 16), __builtin_bit_cast(float, v.x & 0xFFFF0000u),
+                     __builtin_bit_cast(float, v.y << 16), __builtin_bit_cast(float, v.y & 0xFFFF0000u));
+}
+
+// channels cc..cc+3 of part p at input-plane pixel (yy, xx); zero outside
+__device__ __forceinline__ float4 wg_load4(const SrcPart& p, int b, int yy, int xx, int cc, int H, int W, int rnd) {
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (yy < 0 || xx < 0 || yy >= H || xx >= W) return z;
+  int sy, sx;
+  if (p.up) {
+    sy = yy >> 1;
+    sx = xx >> 1;
+  } else {
+    sy = yy - p.oy;
+    sx = xx - p.ox;
+  }
+  if (sy < 0 || sx < 0 || sy >= p.h || sx >= p.w) return z;
+  const int64_t o = (((int64_t)b * p.h + sy) * p.w + sx) * p.stride + p.coff + cc;
+  if (p.bf16) return bf16x4_to_f32(*reinterpret_cast<const uint2*>(p.bf16 + o));
+  float4 v = *reinterpret_cast<const float4*>(p.f32 + o);
+  if (rnd) {
+    v.x = bf16_round(v.x);
+    v.y = bf16_round(v.y);
+    v.z = bf16_round(v.z);
+    v.w = bf16_round(v.w);
+  }
+  return v;
+}
+
+template <int MWG>
+__global__ void __launch_bounds__(CT) k_wgrad_tiled(WgradArgs A) {
+  constexpr int TM = MWG / 4;            // threads along the channel axis
+  constexpr int NWG4 = CT / TM;          // float4 columns per workgroup
+  __shared__ float4 s_g[WG_KP][TM];
+  __shared__ float4 s_x[WG_KP][NWG4];
+  const int tid = threadIdx.x;
+  const int tm = tid % TM, tn = tid / TM;
   const int cin = A.src.a.c + A.src.b.c;
-  const int64_t nw = (int64_t)A.cout * 9 * cin;
-  const int64_t idx = blockIdx.x * (int64_t)CT + threadIdx.x;
-  if (idx >= nw + A.cout) return;
+  const int N = 9 * cin;
+  const int nb = blockIdx.x * NWG4 * 4;
   const int64_t npix = (int64_t)A.B * A.Ho * A.Wo;
   const int64_t p0 = npix * blockIdx.y / gridDim.y, p1 = npix * (blockIdx.y + 1) / gridDim.y;
-  float acc = 0.f;
-  if (idx < nw) {
-    const int co = (int)(idx / (9 * cin));
-    const int tap = (int)((idx / cin) % 9);
-    const int ci = (int)(idx % cin);
-    const int ky = tap / 3, kx = tap % 3;
-    const bool in_a = ci < A.src.a.c;
-    const SrcPart& sp = in_a ? A.src.a : A.src.b;
-    const int cc = in_a ? ci : ci - A.src.a.c;
-    for (int64_t p = p0; p < p1; ++p) {
-      float g = A.dA[p * A.d_stride + co];
-      if (A.mask && !(A.mask[p * A.d_stride + co] > 0.f)) g = 0.f;
-      if (g == 0.f) continue;
-      const int b = (int)(p / ((int64_t)A.Ho * A.Wo));
-      const int r = (int)(p - (int64_t)b * A.Ho * A.Wo);
-      const int yy = A.y0 + r / A.Wo + ky - 1, xx = A.x0 + r % A.Wo + kx - 1;
-      if (yy < 0 || yy >= A.H || xx < 0 || xx >= A.W) continue;
-      int sy, sx;
-      if (sp.up) {
-        sy = yy >> 1;
-        sx = xx >> 1;
-      } else {
-        sy = yy - sp.oy;
-        sx = xx - sp.ox;
+  const int64_t hw = (int64_t)A.Ho * A.Wo;
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+  for (int64_t ps = p0; ps < p1; ps += WG_KP) {
+    for (int e = tid; e < WG_KP * TM; e += CT) {
+      const int kk = e / TM, c4 = e - kk * TM;
+      const int64_t p = ps + kk;
+      float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (p < p1 && 4 * c4 < A.cout) {
+        const int64_t o = p * A.d_stride + 4 * c4;
+        if (A.g_bf16) {
+          g = bf16x4_to_f32(*reinterpret_cast<const uint2*>(A.g_bf16 + o));
+        } else {
+          g = *reinterpret_cast<const float4*>(A.dA + o);
+          if (A.mask) {
+            const float4 m = *reinterpret_cast<const float4*>(A.mask + o);
+            g.x = m.x > 0.f ? g.x : 0.f;
+            g.y = m.y > 0.f ? g.y : 0.f;
+            g.z = m.z > 0.f ? g.z : 0.f;
+            g.w = m.w > 0.f ? g.w : 0.f;
+          }
+        }
       }
-      if (sy < 0 || sx < 0 || sy >= sp.h || sx >= sp.w) continue;
-      acc = fmaf(g, sp.f32[(((int64_t)b * sp.h + sy) * sp.w + sx) * sp.stride + sp.coff + cc], acc);
+      s_g[kk][c4] = g;
     }
-  } else {
-    const int co = (int)(idx - nw);
-    for (int64_t p = p0; p < p1; ++p) {
-      float g = A.dA[p * A.d_stride + co];
-      if (A.mask && !(A.mask[p * A.d_stride + co] > 0.f)) g = 0.f;
-      acc += g;
+    for (int e = tid; e < WG_KP * NWG4; e += CT) {
+      const int kk = e / NWG4, n4 = e - kk * NWG4;
+      const int64_t p = ps + kk;
+      const int n = nb + 4 * n4;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (p < p1) {
+        if (n < N) {
+          const int tap = n / cin, ci = n - tap * cin;
+          const int ky = tap / 3, kx = tap - 3 * ky;
+          const int b = (int)(p / hw);
+          const int r = (int)(p - (int64_t)b * hw);
+          const int yy = A.y0 + r / A.Wo + ky - 1, xx = A.x0 + r % A.Wo + kx - 1;
+          const bool in_a = ci < A.src.a.c;
+          v = wg_load4(in_a ? A.src.a : A.src.b, b, yy, xx, in_a ? ci : ci - A.src.a.c, A.H, A.W, A.round_in);
+        } else if (n == N) {
+          v.x = 1.f;
+        }
+      }
+      s_x[kk][n4] = v;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < WG_KP; ++kk) {
+      const float4 g = s_g[kk][tm], x = s_x[kk][tn];
+      const float gv[4] = {g.x, g.y, g.z, g.w}, xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(gv[i], xv[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  float* out = A.partial + (int64_t)blockIdx.y * ((int64_t)A.cout * N + A.cout);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int co = 4 * tm + i;
+    if (co >= A.cout) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = nb + 4 * tn + j;
+      if (n < N)
+        out[(int64_t)co * N + n] = acc[i][j];
+      else if (n == N)
+        out[(int64_t)A.cout * N + co] = acc[i][j];
     }
   }
-  A.partial[(int64_t)blockIdx.y * (nw + A.cout) + idx] = acc;
 }
 
 __global__ void k_reduce_partials(const float* __restrict__ partial, int nchunk, int64_t n, float* __restrict__ out) {
@@ -344,9 +428,18 @@ int ls_prep_weights(const float* w, float* wt, float* wd, hipStream_t st) {
 int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st) {
   const int cin = a.src.a.c + a.src.b.c;
   const int64_t n = (int64_t)a.cout * 9 * cin + a.cout;
-  dim3 grid(nblk(n), a.nchunk);
-  LS_TRACE("wgrad_f32", st);
-  hipLaunchKernelGGL(k_wgrad_f32, grid, dim3(CT), 0, st, a);
+  // every part and the gradient are read four channels at a time
+  if (a.cout % 4 || a.src.a.c % 4 || a.src.b.c % 4 || a.d_stride % 4) return LS_ENOTIMPL;
+  const int mwg = a.cout <= 16 ? 16 : (a.cout <= 32 ? 32 : 64);
+  if (a.cout > 64) return LS_ENOTIMPL;
+  const int cols = 4 * (CT / (mwg / 4));
+  dim3 grid((unsigned)((9 * cin + 1 + cols - 1) / cols), (unsigned)a.nchunk);
+  LS_TRACE("wgrad", st);
+  switch (mwg) {
+    case 16: hipLaunchKernelGGL(k_wgrad_tiled<16>, grid, dim3(CT), 0, st, a); break;
+    case 32: hipLaunchKernelGGL(k_wgrad_tiled<32>, grid, dim3(CT), 0, st, a); break;
+    default: hipLaunchKernelGGL(k_wgrad_tiled<64>, grid, dim3(CT), 0, st, a); break;
+  }
   hipLaunchKernelGGL(k_reduce_partials, dim3(nblk(n)), dim3(CT), 0, st, a.partial, a.nchunk, n, grad_w_layer);
   LS_LAUNCH_CHECK();
   return LS_OK;

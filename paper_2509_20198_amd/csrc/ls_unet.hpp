@@ -38,10 +38,12 @@ struct WgradArgs {
   int B, H, W;
   int y0, x0, Ho, Wo;
   int cout;
-  const float* dA;       // gradient at the conv output, [B][Ho][Wo][d_stride]
-  const float* mask;     // forward activation (ReLU mask) or null, same layout
+  const float* dA;          // gradient at the conv output, [B][Ho][Wo][d_stride]
+  const float* mask;        // FP32 forward activation (ReLU mask) or null, same layout
+  const uint16_t* g_bf16;   // instead of dA/mask: the masked gradient already rounded to BF16
   int d_stride;
-  float* partial;        // [nchunk][cout*9*cin + cout]
+  int round_in;             // round FP32-stored inputs to BF16 (BF16 path)
+  float* partial;           // [nchunk][cout*9*cin + cout]
   int nchunk;
 };
 

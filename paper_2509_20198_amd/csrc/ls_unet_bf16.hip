@@ -329,7 +329,118 @@ __global__ void k_round_bf16(const float* __restrict__ w, uint16_t* __restrict__
   if (i < n) out[i] = f2bf(w[i]);
 }
 
+// Gradient channels the dgrad of layer l reads: cout, except the head whose
+// 4-channel output gradient is stored padded to 8 (one 16-byte load).
+__host__ __device__ __forceinline__ int dgrad_cg(int l) { return l == LS_NLAYER - 1 ? 8 : LS_LAYERS[l].cout; }
+__host__ __device__ __forceinline__ int dgrad_kpad(int l) { return (9 * dgrad_cg(l) + 31) / 32 * 32; }
+
+// dgrad weights, per layer [ceil16(cin)][Kpad']: row ci, k = tap' * cg + co
+// holds W[co][8 - tap'][ci] (the kernel turned by 180 degrees and
+// transposed), zero for padding.
+__global__ void k_pack_dgrad_bf16(const uint16_t* __restrict__ w, uint16_t* __restrict__ packed) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t off = 0, woff = 0;
+  for (int l = 0; l < LS_NLAYER; ++l) {
+    const int cin = LS_LAYERS[l].cin, cout = LS_LAYERS[l].cout, cg = dgrad_cg(l);
+    const int Kpad = dgrad_kpad(l), Npad = (cin + 15) / 16 * 16;
+    const int64_t n = (int64_t)Npad * Kpad;
+    if (i >= off && i < off + n) {
+      const int ci = (int)((i - off) / Kpad), k = (int)((i - off) % Kpad);
+      uint16_t v = 0;
+      if (ci < cin && k < 9 * cg) {
+        const int tf = k / cg, co = k - tf * cg;
+        if (co < cout) v = w[woff + ((int64_t)co * 9 + (8 - tf)) * cin + ci];
+      }
+      packed[i] = v;
+      return;
+    }
+    off += n;
+    woff += (int64_t)cout * 9 * cin + cout;
+  }
+}
+
+// out = BF16(g where the forward activation is positive, else 0)
+__global__ void k_mask_round_bf16(const float* __restrict__ g, const uint16_t* __restrict__ act,
+                                  uint16_t* __restrict__ out, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = f2bf(bf2f(act[i]) > 0.f ? g[i] : 0.f);
+}
+
+// [npix][4] FP32 -> [npix][8] BF16 with channels 4..7 zero
+__global__ void k_embed8_bf16(const float* __restrict__ g, uint16_t* __restrict__ out, int64_t npix) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= npix * 8) return;
+  const int c = (int)(i & 7);
+  out[i] = c < 4 ? f2bf(g[(i >> 3) * 4 + c]) : (uint16_t)0;
+}
+
 }  // namespace
+
+size_t ls_bf16_dpacked_offset(int l) {
+  size_t off = 0;
+  for (int k = 0; k < l; ++k) off += (size_t)((LS_LAYERS[k].cin + 15) / 16 * 16) * dgrad_kpad(k);
+  return off;
+}
+
+size_t ls_bf16_dpacked_total() { return ls_bf16_dpacked_offset(LS_NLAYER); }
+
+int ls_bf16_prep_dgrad_weights(const uint16_t* w_bf16, uint16_t* packed, hipStream_t st) {
+  const int64_t n = (int64_t)ls_bf16_dpacked_total();
+  hipLaunchKernelGGL(k_pack_dgrad_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w_bf16, packed);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_bf16_mask_round(const float* g, const uint16_t* act, uint16_t* out, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_mask_round_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, act, out, n);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_bf16_embed8(const float* g, uint16_t* out, int64_t npix, hipStream_t st) {
+  hipLaunchKernelGGL(k_embed8_bf16, dim3((unsigned)((npix * 8 + 255) / 256)), dim3(256), 0, st, g, out, npix);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+// Input gradient of layer l over the whole H x H plane: the conv of the
+// (masked, BF16) output gradient `s` with the turned weights, FP32 result
+// [B][H][H][cin].
+int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked, float* out, hipStream_t st) {
+  const int cin = LS_LAYERS[l].cin;
+  if (s.a.c + s.b.c != dgrad_cg(l)) return LS_EINVAL;
+  ConvArgsB a;
+  a.src = s;
+  a.B = B;
+  a.H = H;
+  a.W = H;
+  a.y0 = 0;
+  a.x0 = 0;
+  a.Ho = H;
+  a.Wo = H;
+  a.wp = dpacked + ls_bf16_dpacked_offset(l);
+  a.Kpad = dgrad_kpad(l);
+  a.bias = nullptr;
+  a.cout = cin;
+  a.relu = 0;
+  a.out_bf16 = nullptr;
+  a.out_f32 = out;
+  a.out_stride = cin;
+  const int64_t npix = (int64_t)B * H * H;
+  const int64_t per_block = 16 * MT * WAVES;
+  dim3 grid((unsigned)((npix + per_block - 1) / per_block));
+  LS_TRACE("dgrad_bf16", st);
+  switch ((cin + 15) / 16) {
+    case 1: hipLaunchKernelGGL(k_conv_bf16<1>, grid, dim3(64 * WAVES), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_conv_bf16<2>, grid, dim3(64 * WAVES), 0, st, a); break;
+    case 3: hipLaunchKernelGGL(k_conv_bf16<3>, grid, dim3(64 * WAVES), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_conv_bf16<4>, grid, dim3(64 * WAVES), 0, st, a); break;
+    case 6: hipLaunchKernelGGL(k_conv_bf16<6>, grid, dim3(64 * WAVES), 0, st, a); break;
+    default: return LS_ENOTIMPL;
+  }
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
 
 int ls_bf16_kpad(int l) { return (9 * LS_LAYERS[l].cin + 31) / 32 * 32; }
 

@@ -145,3 +145,122 @@ def test_full_batch_1024_bf16_and_fp32_sampled():
     t16 = tex16.cpu().numpy()[ks].astype(np.float64)
     assert np.abs(t32[..., 0] - ref[..., 0]).max() <= 1e-4
     assert rms_per_tile(t16[..., 0], ref[..., 0]).max() <= 0.05
+
+
+def _bf16(a):
+    """Round to BF16 (nearest even) and back, in float64."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# BF16 form.  Every conv operand (weights, input, activations, the masked
+# gradient) is rounded to BF16, products accumulate in FP32 and the ReLU masks
+# come from BF16 activations.  oracle.unet_bf16 evaluates the same form in
+# FP64 between the same rounding points.  Layer by layer the two agree except
+# for rounding ties that FP32 and FP64 accumulation decide differently (about
+# 1e-4 of the values, one BF16 step each); through the network these flip
+# later roundings and ReLU masks, so for random weights the end-to-end
+# distance is set by the form itself, not by the kernels.  Hence two checks:
+#  * all-active weights (non-negative, positive biases: no deep mask can
+#    flip): the 1e-3 gate applies per layer, forward and backward;
+#  * random weights: the GPU must be no farther from the FP64 reference than
+#    a few times the distance of the same form accumulated in FP32 on the
+#    CPU (an equally valid order).
+# The distance to the exact gradient at BF16-rounded weights and inputs is
+# printed as well.
+
+
+def _layer_rel(a, b):
+    out, off = [], 0
+    for name, ci, co in synth.UNET_SHAPES:
+        sz = co * 9 * ci + co
+        out.append((name, np.linalg.norm(a[off:off + sz] - b[off:off + sz]) /
+                    max(np.linalg.norm(b[off:off + sz]), 1e-30)))
+        off += sz
+    return out
+
+
+def _bf16_case(all_active):
+    from oracle import unet_bf16
+
+    w, xo, cz = _x_from_oracle(2, seed=7)
+    xo = xo[:3]
+    wts = synth.unet_weights(1, head_std=0.05, bias_std=0.05)
+    if all_active:
+        wts = unet_bf16.all_active_weights(wts)
+    wts = wts.astype(np.float32).astype(np.float64)
+    x32 = xo.astype(np.float32).astype(np.float64)
+    G = np.random.default_rng(3).standard_normal((xo.shape[0], 64, 64, 4))
+    g = ls.Grid.of(w.region)
+    xt = torch.from_numpy(x32.astype(np.float32)).cuda()
+    wt = torch.from_numpy(wts.astype(np.float32)).cuda()
+    gt = torch.from_numpy(G.astype(np.float32)).cuda()
+    wb = ls.pack_weights_bf16(wt)
+    y, _ = ls.refine_tiles(wt, xt, None, g, ls.BF16, w_bf16=wb, want_tex=False)
+    gw, gx = ls.refine_backward(wt, xt, gt, g, ls.BF16, w_bf16=wb, want_grad_x=True)
+    torch.cuda.synchronize()
+    return wts, x32, G, y.cpu().numpy().astype(np.float64), gw.cpu().numpy().astype(np.float64), \
+        gx.cpu().numpy().astype(np.float64)
+
+
+def test_bf16_all_active_matches_bf16_reference():
+    from oracle import unet_bf16
+
+    wts, x32, G, y, gw, gx = _bf16_case(True)
+    y_ref = unet_bf16.forward(wts, x32, 64, 16)
+    gw_ref, gx_ref = unet_bf16.backward(wts, x32, G, 64, 16)
+    ey = np.abs(y - y_ref).max() / np.abs(y_ref).max()
+    ex = np.linalg.norm(gx - gx_ref) / np.linalg.norm(gx_ref)
+    layers = _layer_rel(gw, gw_ref)
+    print(f"all-active bf16: forward {ey:.2e}, grad_x {ex:.2e}; grad_w per layer " +
+          " ".join(f"{n} {r:.1e}" for n, r in layers))
+    assert ey <= 1e-3 and ex <= 1e-3
+    for n, r in layers:
+        assert r <= 1e-3, (n, r)
+
+
+def test_bf16_random_weights_within_accumulation_spread():
+    from oracle import unet_bf16
+
+    wts, x32, G, y, gw, gx = _bf16_case(False)
+    y64 = unet_bf16.forward(wts, x32, 64, 16)
+    y32 = unet_bf16.forward(wts, x32, 64, 16, accum=torch.float32)
+    g64, gx64 = unet_bf16.backward(wts, x32, G, 64, 16)
+    g32, gx32 = unet_bf16.backward(wts, x32, G, 64, 16, accum=torch.float32)
+    gex, _ = oracle.unet_backward(_bf16(wts), _bf16(x32), G, 64, 16)
+    ey, ey_alt = (np.abs(v - y64).max() / np.abs(y64).max() for v in (y, y32))
+    ex, ex_alt = (np.linalg.norm(v - gx64) / np.linalg.norm(gx64) for v in (gx, gx32))
+    lg, la = _layer_rel(gw, g64), _layer_rel(g32, g64)
+    rel_ex = np.linalg.norm(gw - gex) / np.linalg.norm(gex)
+    print(f"random-weight bf16: forward {ey:.2e} (fp32-accum ref {ey_alt:.2e}), grad_x {ex:.2e} ({ex_alt:.2e}), "
+          f"grad_w vs exact gradient {rel_ex:.2e}")
+    for (n, r), (_, ra) in zip(lg, la):
+        print(f"  {n}: {r:.2e} (fp32-accum ref {ra:.2e})")
+        assert r <= 3 * ra + 1e-3, (n, r, ra)
+    assert ey <= 3 * ey_alt + 1e-5 and ex <= 3 * ex_alt + 1e-3
+
+
+def test_backward_bf16_saved_activations_equal_recompute():
+    w, xo, wts, G, g, xt, wt, gt, wb, gw, gx = _backward_case(ls.BF16, want_gx=False)
+    act = torch.empty(ls.act_bytes(g, xt.shape[0], ls.BF16), dtype=torch.uint8, device="cuda")
+    ls.refine_tiles(wt, xt, None, g, ls.BF16, w_bf16=wb, act_save=act, want_tex=False)
+    gw2, _ = ls.refine_backward(wt, xt, gt, g, ls.BF16, w_bf16=wb, act_save=act)
+    torch.cuda.synchronize()
+    assert np.array_equal(gw2.cpu().numpy().astype(np.float64), gw)
+
+
+@pytest.mark.parametrize("precision", [ls.FP32, ls.BF16])
+def test_refine_fn_autograd_probe_loss(precision):
+    """RefineFn under torch.autograd: the probe loss <G, y> gives grad_w and
+    grad_x equal to refine_backward's, with saved activations and with
+    recomputation."""
+    w, xo, wts, G, g, xt, wt, gt, wb, gw, gx = _backward_case(precision)
+    for save in (True, False):
+        x_ = xt.clone().requires_grad_(True)
+        w_ = wt.clone().requires_grad_(True)
+        y = ls.RefineFn.apply(x_, w_, g, precision, save)
+        (y * gt).sum().backward()
+        torch.cuda.synchronize()
+        assert np.array_equal(w_.grad.cpu().numpy().astype(np.float64), gw)
+        assert np.array_equal(x_.grad.cpu().numpy().astype(np.float64), gx)
