@@ -162,6 +162,12 @@ def main():
         ls.recon_tiles(g, x, y, z, rgb, tl, x_out=x_out, cz_out=cz, status=st, ws=ws_recon)
         ls.refine_tiles(w, x_out, cz, g, ls.FP32, tex_out=tex32, want_y=False, ws=ws32)
 
+    # ---------------------------------------------------------------- conv tilings
+    from paper_2509_20198_amd import autotune as AT
+
+    tune = AT.autotune(g, nt, ls.BF16, passes=(0,), reps=5, force=True)
+    log(f"autotuned BF16 forward tilings: {tune['ms_default']:.3f} -> {tune['ms_tuned']:.3f} ms")
+
     # ---------------------------------------------------------------- graph
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -237,6 +243,9 @@ def main():
         "fp32_plain": {"tiles_per_s": nt / (ms32 * 1e-3), "ms_per_step": ms32},
         "bf16_vs_fp32": ms32 / ms16,
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kernels.items())},
+        "autotune_bf16_forward": {"choice": tune["choice"], "refine_ms_default": tune["ms_default"],
+                                  "refine_ms_tuned": tune["ms_tuned"],
+                                  "configs": "0 direct (4 pixel tiles/wave), 1 LDS 16x16 tile, 2 direct (2 pixel tiles/wave)"},
         "tile_status_nonzero": int((status != 0).sum()),
     }
 

@@ -110,6 +110,7 @@ ConvArgs conv_args(const ConvSrc& s, int B, int H, const float* wt, const float*
   a.out = out;
   a.out_stride = a.cout;
   a.out_coff = 0;
+  a.cob_max = ls_cob_for_config(ls_conv_config_get(l, LS_FP32, 0));
   return a;
 }
 
@@ -180,7 +181,8 @@ int wgrad(const ConvSrc& s, int B, int H, int l, const float* dA, const float* m
   a.round_in = 0;
   a.partial = partial;
   const int64_t npix = (int64_t)B * Ho * Wo;
-  a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(WG_MAX_CHUNKS, npix / 256));
+  const int chunks = ls_wgrad_chunks_for_config(ls_conv_config_get(l, LS_FP32, 2));
+  a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, npix / 256));
   return ls_wgrad_f32(a, grad_w + ls_layer_w_offset(l), st);
 }
 
@@ -205,7 +207,8 @@ int wgrad_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* g, int d_s
   a.round_in = 1;
   a.partial = partial;
   const int64_t npix = (int64_t)B * Ho * Wo;
-  a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(WG_MAX_CHUNKS, npix / 256));
+  const int chunks = ls_wgrad_chunks_for_config(ls_conv_config_get(l, LS_BF16, 2));
+  a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, npix / 256));
   return ls_wgrad_f32(a, grad_w + ls_layer_w_offset(l), st);
 }
 
@@ -238,6 +241,7 @@ int dgrad(const float* wd, int l, const float* dA, const float* mask, int B, int
   a.out = out;
   a.out_stride = cin;
   a.out_coff = 0;
+  a.cob_max = ls_cob_for_config(ls_conv_config_get(l, LS_FP32, 1));
   return ls_conv_f32(a, st);
 }
 
@@ -270,6 +274,7 @@ int backward_f32(const float* w, const float* wd, const float* x, const float* a
     a.out = W.dXC;
     a.out_stride = 24;
     a.out_coff = 0;
+    a.cob_max = ls_cob_for_config(ls_conv_config_get(HEAD, LS_FP32, 1));
     LS_TRY(ls_conv_f32(a, st));
   }
   LS_TRY(wgrad(two(P(iA10, 16, R), X), B, R, HEAD, grad_y, nullptr, 4, pad, pad, res, res, grad_w, W.partial, st));

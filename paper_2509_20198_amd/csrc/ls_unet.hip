@@ -386,7 +386,13 @@ SrcPart src_none() { return src_plain(nullptr, 0, 0, 0, 0, 0, nullptr); }
 int ls_conv_f32(const ConvArgs& a, hipStream_t st) {
   const int64_t npix = (int64_t)a.B * a.Ho * a.Wo;
   const bool mask = (a.src.a.mask != nullptr) || (a.src.b.mask != nullptr);
-  const int cob = a.cout % 32 == 0 ? 32 : (a.cout % 16 == 0 ? 16 : (a.cout % 8 == 0 ? 8 : 4));
+  const int cap = a.cob_max > 0 ? a.cob_max : 32;
+  int cob = 4;
+  for (int c = 32; c >= 4; c /= 2)
+    if (c <= cap && a.cout % c == 0) {
+      cob = c;
+      break;
+    }
   if (a.cout % 4) return LS_ENOTIMPL;
   dim3 grid(nblk(npix), a.cout / cob);
   LS_TRACE("conv_f32", st);

@@ -31,6 +31,7 @@ struct ConvArgs {
   int relu;
   float* out;            // [B][Ho][Wo][out_stride]
   int out_stride, out_coff;
+  int cob_max;           // largest output-channel block per thread (32, 16, 8 or 4)
 };
 
 struct WgradArgs {
@@ -46,6 +47,13 @@ struct WgradArgs {
   float* partial;           // [nchunk][cout*9*cin + cout]
   int nchunk;
 };
+
+// Tiling choices per (layer, precision, pass), set by ls_set_conv_config.
+int ls_conv_config_get(int layer, int precision, int pass);
+// FP32 conv: config 0..3 -> channel block cap 32, 16, 8, 4
+inline int ls_cob_for_config(int c) { return c <= 0 ? 32 : (c == 1 ? 16 : (c == 2 ? 8 : 4)); }
+// weight gradient: config 0..2 -> pixel chunks 512, 256, 128
+inline int ls_wgrad_chunks_for_config(int c) { return c <= 0 ? 512 : (c == 1 ? 256 : 128); }
 
 SrcPart src_plain(const float* p, int c, int h, int w, int stride, int coff, const float* mask);
 SrcPart src_none();

@@ -3,7 +3,7 @@
 // Each 3x3 conv is an implicit GEMM: rows = output pixels (NHWC order),
 // columns = output channels, reduction k = tap*cin + ci (tap-major, so a run
 // of 8 consecutive k is 8 consecutive channels of one input pixel: one
-// 16-byte load).  A wave owns 16*MT pixels x all output channels and issues
+// 16-byte load).  A wave owns 16*MT pixels (MT = 2 or 4) x all output channels and issues
 // v_mfma_f32_16x16x32_bf16 (FP32 accumulation); lane l supplies A row l%16
 // and B column l%16 with k in [8*(l/16), 8*(l/16)+8) of each 32-wide step,
 // and receives D rows 4*(l/16)..+3 of column l%16.  Bias and ReLU are
@@ -21,7 +21,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int WAVES = 4;
-constexpr int MT = 4;  // 16-pixel tiles per wave
 
 struct ConvArgsB {
   ConvSrc src;
@@ -77,7 +76,10 @@ __device__ __forceinline__ u16x8 load8(const ConvSrc& s, int b, int yy, int xx, 
   return r;
 }
 
-template <int NT>
+int launch_direct(const ConvArgsB& a, int nt, int mt, int64_t npix, hipStream_t st);
+
+// NT 16-channel output tiles, MT 16-pixel tiles per wave
+template <int NT, int MT>
 __global__ void __launch_bounds__(64 * WAVES) k_conv_bf16(ConvArgsB A) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t npix = (int64_t)A.B * A.Ho * A.Wo;
@@ -426,20 +428,10 @@ int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked
   a.out_bf16 = nullptr;
   a.out_f32 = out;
   a.out_stride = cin;
-  const int64_t npix = (int64_t)B * H * H;
-  const int64_t per_block = 16 * MT * WAVES;
-  dim3 grid((unsigned)((npix + per_block - 1) / per_block));
   LS_TRACE("dgrad_bf16", st);
-  switch ((cin + 15) / 16) {
-    case 1: hipLaunchKernelGGL(k_conv_bf16<1>, grid, dim3(64 * WAVES), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_conv_bf16<2>, grid, dim3(64 * WAVES), 0, st, a); break;
-    case 3: hipLaunchKernelGGL(k_conv_bf16<3>, grid, dim3(64 * WAVES), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_conv_bf16<4>, grid, dim3(64 * WAVES), 0, st, a); break;
-    case 6: hipLaunchKernelGGL(k_conv_bf16<6>, grid, dim3(64 * WAVES), 0, st, a); break;
-    default: return LS_ENOTIMPL;
-  }
-  LS_LAUNCH_CHECK();
-  return LS_OK;
+  // config 0: 4 pixel tiles per wave, 1: 2
+  const int mt = ls_conv_config_get(l, LS_BF16, 1) == 1 ? 2 : 4;
+  return launch_direct(a, (cin + 15) / 16, mt, (int64_t)B * H * H, st);
 }
 
 int ls_bf16_kpad(int l) { return (9 * LS_LAYERS[l].cin + 31) / 32 * 32; }
@@ -468,8 +460,37 @@ int ls_bf16_prep_weights(const uint16_t* w_bf16, uint16_t* packed, hipStream_t s
 
 namespace {
 
+// Direct kernel over npix output pixels: nt channel tiles, mt pixel tiles per wave.
+int launch_direct(const ConvArgsB& a, int nt, int mt, int64_t npix, hipStream_t st) {
+  const int64_t per_block = 16 * mt * WAVES;
+  dim3 grid((unsigned)((npix + per_block - 1) / per_block));
+#define LS_DIRECT(N, M) hipLaunchKernelGGL((k_conv_bf16<N, M>), grid, dim3(64 * WAVES), 0, st, a)
+  if (mt == 2) {
+    switch (nt) {
+      case 1: LS_DIRECT(1, 2); break;
+      case 2: LS_DIRECT(2, 2); break;
+      case 3: LS_DIRECT(3, 2); break;
+      case 4: LS_DIRECT(4, 2); break;
+      case 6: LS_DIRECT(6, 2); break;
+      default: return LS_ENOTIMPL;
+    }
+  } else {
+    switch (nt) {
+      case 1: LS_DIRECT(1, 4); break;
+      case 2: LS_DIRECT(2, 4); break;
+      case 3: LS_DIRECT(3, 4); break;
+      case 4: LS_DIRECT(4, 4); break;
+      case 6: LS_DIRECT(6, 4); break;
+      default: return LS_ENOTIMPL;
+    }
+  }
+#undef LS_DIRECT
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
 int conv_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* packed, const float* w, uint16_t* out_bf16,
-              float* out_f32, int relu, int y0, int x0, int Ho, int Wo, hipStream_t st) {
+              float* out_f32, int relu, int y0, int x0, int Ho, int Wo, int mt, hipStream_t st) {
   ConvArgsB a;
   a.src = s;
   a.B = B;
@@ -487,19 +508,9 @@ int conv_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* packed, con
   a.out_bf16 = out_bf16;
   a.out_f32 = out_f32;
   a.out_stride = a.cout;
-  const int64_t npix = (int64_t)B * Ho * Wo;
-  const int64_t per_block = 16 * MT * WAVES;
-  dim3 grid((unsigned)((npix + per_block - 1) / per_block));
   const int nt = (a.cout + 15) / 16;
   LS_TRACE("conv_bf16", st);
-  switch (nt) {
-    case 1: hipLaunchKernelGGL(k_conv_bf16<1>, grid, dim3(64 * WAVES), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_conv_bf16<2>, grid, dim3(64 * WAVES), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_conv_bf16<4>, grid, dim3(64 * WAVES), 0, st, a); break;
-    default: return LS_ENOTIMPL;
-  }
-  LS_LAUNCH_CHECK();
-  return LS_OK;
+  return launch_direct(a, nt, mt, (int64_t)B * Ho * Wo, st);
 }
 
 int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed, const float* w, uint16_t* out_bf16,
@@ -593,7 +604,9 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   uint16_t* A10 = A9 + 16 * f * B;
   SrcPart X = src_plain(x, 8, R, R, 8, 0, nullptr);
   const SrcPart none = src_none();
-  // per layer: tiling variant 0 = direct (A from global memory), 1 = LDS-staged tile (default)
+  // per layer: tiling variant 0 = direct (operands from global memory, 4 pixel
+  // tiles per wave), 1 = LDS-staged 16 x 16 tile (default), 2 = direct with 2
+  // pixel tiles per wave
   auto variant = [&](int l) {
     const int c = ls_conv_config_get(l, LS_BF16, 0);
     return c < 0 ? 1 : c;
@@ -607,7 +620,7 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
       if (pooled && !fuse) return pool_bf16(out, pooled, B, H, LS_LAYERS[l].cout, st);
       return LS_OK;
     }
-    LS_TRYB(conv_bf16(s, B, H, l, packed, w, out, nullptr, 1, 0, 0, H, H, st));
+    LS_TRYB(conv_bf16(s, B, H, l, packed, w, out, nullptr, 1, 0, 0, H, H, variant(l) == 2 ? 2 : 4, st));
     if (pooled) return pool_bf16(out, pooled, B, H, LS_LAYERS[l].cout, st);
     return LS_OK;
   };
@@ -629,5 +642,5 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
     return conv_bf16_lds(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,
                          gi.res, gi.res, st);
   return conv_bf16(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, 0, gi.pad, gi.pad, gi.res, gi.res,
-                   st);
+                   variant(10) == 2 ? 2 : 4, st);
 }
