@@ -235,7 +235,18 @@ struct Tile {
   double bw;  // bucket width in raw units
 };
 
-__device__ __forceinline__ int bucket_1d(int w, int G, int W2) { return (int)(((int64_t)w * G) / W2); }
+// floor(w * G / W2) for 0 <= w < W2 <= 2^17 and G <= 88 (all products below
+// 2^24): a float reciprocal estimate, off by at most one, then an exact
+// integer correction.
+__device__ __forceinline__ int bucket_1d(int w, int G, int W2) {
+  const int num = w * G;
+  int q = (int)((float)num * __builtin_amdgcn_rcpf((float)W2));
+  if (q * W2 > num)
+    --q;
+  else if ((q + 1) * W2 <= num)
+    ++q;
+  return q;
+}
 
 __device__ __forceinline__ double orient_d(double ax, double ay, double bx, double by, double px, double py) {
   // exact: |differences| < 2^17, products < 2^34, result < 2^35
@@ -414,17 +425,19 @@ __device__ int third_left(const Tile& T, int a, int b) {
   int best = -1;
   int2 C = make_int2(0, 0);
   double ocx = 0.0, ocy = 0.0, rho = 0.0;  // circle centre (tile-local) and radius
+  // orient(a, b, .) is linear with gradient (-fby, fbx): over a rectangle it
+  // peaks at the corner these signs pick
+  const bool hi_x = fby <= 0.0, hi_y = fbx >= 0.0;
+  const double inv_ll = 1.0 / sqrt(bl);
+  double lim2 = 0.0;  // squared reach of the current circle, with margin
   auto visit = [&](int qx, int qy) {
     // bucket rectangle in tile-local coordinates, rounded outwards to integers
     const double x0 = floor(qx * T.bw) - T.H - 1.0, x1 = ceil((qx + 1) * T.bw) - T.H + 1.0;
     const double y0 = floor(qy * T.bw) - T.H - 1.0, y1 = ceil((qy + 1) * T.bw) - T.H + 1.0;
-    const double o00 = orient_d(ax, ay, bx, by, x0, y0), o10 = orient_d(ax, ay, bx, by, x1, y0);
-    const double o01 = orient_d(ax, ay, bx, by, x0, y1), o11 = orient_d(ax, ay, bx, by, x1, y1);
-    if (fmax(fmax(o00, o10), fmax(o01, o11)) <= 0.0) return;
+    if (orient_d(ax, ay, bx, by, hi_x ? x1 : x0, hi_y ? y1 : y0) <= 0.0) return;
     if (best >= 0) {
       const double dx = fmax(fmax(x0 - ocx, ocx - x1), 0.0), dy = fmax(fmax(y0 - ocy, ocy - y1), 0.0);
-      const double lim = rho * (1.0 + 1e-9) + 2.0;
-      if (dx * dx + dy * dy > lim * lim) return;
+      if (dx * dx + dy * dy > lim2) return;
     }
     const int bi = qy * T.G + qx;
     const int e = T.boff[bi + 1];
@@ -432,25 +445,34 @@ __device__ int third_left(const Tile& T, int a, int b) {
       if (p == a || p == b) continue;
       const int2 P = T.uv[p];
       if (orient_d(ax, ay, bx, by, P.x, P.y) <= 0.0) continue;
-      if (best >= 0 && incircle_sos(a, b, best, p, A, B, C, P) <= 0) continue;
+      if (best >= 0) {
+        // clearly outside the current circle: no need for the exact test (the
+        // margin covers the rounding of the centre and radius)
+        const double ex = P.x - ocx, ey = P.y - ocy;
+        if (ex * ex + ey * ey > lim2) continue;
+        if (incircle_sos(a, b, best, p, A, B, C, P) <= 0) continue;
+      }
       best = p;
       C = P;
       // circumcircle of (a, b, p) relative to a
       const double cx = P.x - ax, cy = P.y - ay;
       const double cl = cx * cx + cy * cy;
-      const double D = 2.0 * (fbx * cy - fby * cx);
-      const double ox = (cy * bl - fby * cl) / D, oy = (fbx * cl - cx * bl) / D;
+      const double iD = 0.5 / (fbx * cy - fby * cx);
+      const double ox = (cy * bl - fby * cl) * iD, oy = (fbx * cl - cx * bl) * iD;
       rho = sqrt(ox * ox + oy * oy);
       ocx = ox + ax;
       ocy = oy + ay;
+      {
+        const double lim = rho * (1.0 + 1e-9) + 2.0;
+        lim2 = lim * lim;
+      }
       // signed distance of the centre from the line, > 0 on the left
-      const double ll = sqrt(bl);
-      const double dc = (fbx * oy - fby * ox) / ll;
+      const double dc = (fbx * oy - fby * ox) * inv_ll;
       double cx0, cx1, cy0, cy1;
       if (dc <= 0.0) {
         // sagitta rho - |dc| = (|ab|/2)^2 / (rho + |dc|), free of cancellation
         const double h = bl / (4.0 * (rho - dc)) * (1.0 + 1e-9);
-        const double nx = -fby / ll * h, ny = fbx / ll * h;
+        const double nx = -fby * inv_ll * h, ny = fbx * inv_ll * h;
         cx0 = fmin(fmin(ax, bx), fmin(ax + nx, bx + nx));
         cx1 = fmax(fmax(ax, bx), fmax(ax + nx, bx + nx));
         cy0 = fmin(fmin(ay, by), fmin(ay + ny, by + ny));
