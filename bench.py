@@ -20,8 +20,10 @@ error of the GPU result).  Secondary figures: the full-resolution splat
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,6 +40,23 @@ METRIC = "heightmap tiles/s, BF16 batched vs FP32 plain at ≤0.05 m RMS vs FP64
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+
+
+def recorded_traffic(kernel_source: str, profile: str):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    try:
+        with open(os.path.join(ROOT, "profiles", profile)) as f:
+            text = f.read()
+        with open(os.path.join(ROOT, "paper_2509_20198_amd", "csrc", kernel_source), "rb") as f:
+            src = f.read()
+    except OSError:
+        return None
+    sha = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    val = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not (sha and val) or hashlib.sha256(src).hexdigest() != sha.group(1):
+        return None
+    return int(val.group(1))
 
 
 def log(msg):
@@ -218,8 +237,10 @@ def main():
         ms_dom = kernels[dom]["ms_per_step"]
         bytes_step = nt * R * R * 8 * 4
         ach = bytes_step / (ms_dom * 1e-3) / 1e9
+        traffic = recorded_traffic("ls_recon.hip", "recon_tile_batch_1024_traffic.md") if dom == "recon_tile" else None
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None, "avg_launch_ms": ms_dom / kernels[dom]["launches_per_step"],
+                "frac": ach / PEAK_HBM_GBS, "traffic": traffic, "traffic_unit": "HBM bytes per launch (counters)",
+                "avg_launch_ms": ms_dom / kernels[dom]["launches_per_step"],
                 "algorithmic_per_step": f"{bytes_step / 1e6:.1f} MB written (x_out)"}
     log(f"dominant kernel group: {dom} ({kernels[dom]['ms_per_step']:.3f} ms/step)")
 
