@@ -42,7 +42,7 @@ extern "C" {
  * paper's 16-texel ring, Section 3.3), covering the window
  * [c - H, c + H) with c the tile centre and H = tile_size/2 + pad*cell.
  * Requirements: tile_size % res == 0, cell even, R % 4 == 0, pad >= 0,
- * 1 <= res, H < 2^16.5 raw units after scaling checks (H <= 65535). */
+ * 1 <= res, H <= 65535 raw units, |origin_x|, |origin_y| <= 2^40. */
 typedef struct ls_grid {
   int64_t origin_x, origin_y;
   int32_t tile_size;

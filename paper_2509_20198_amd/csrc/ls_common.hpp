@@ -76,6 +76,9 @@ static inline int ls_grid_info(const ls_grid* g, LsGridInfo* gi) {
   if (R % 4 || R > 4096) return LS_ERANGE;
   const int64_t H = (int64_t)g->tile_size / 2 + (int64_t)g->pad * C;
   if (H > 65535) return LS_ERANGE;  // keeps exact predicates in range
+  // origins within 2^40 raw units keep point-to-origin differences exact in double
+  const int64_t lim = (int64_t)1 << 40;
+  if (g->origin_x < -lim || g->origin_x > lim || g->origin_y < -lim || g->origin_y > lim) return LS_ERANGE;
   gi->ox = g->origin_x;
   gi->oy = g->origin_y;
   gi->S = g->tile_size;
@@ -90,12 +93,6 @@ static inline int ls_grid_info(const ls_grid* g, LsGridInfo* gi) {
   gi->scale_z = g->scale_z;
   gi->offset_z = g->offset_z;
   return LS_OK;
-}
-
-__device__ __forceinline__ int64_t ls_floordiv(int64_t a, int64_t b) {
-  int64_t q = a / b;
-  if ((a % b != 0) && ((a < 0) != (b < 0))) q -= 1;
-  return q;
 }
 
 // Shared U-Net description (HIP side).

@@ -45,6 +45,7 @@ constexpr int SORT_LDS = 16384;          // bin segments up to this size sort in
 
 struct BinParams {
   int64_t ox, oy;
+  double invS;  // 1 / S
   int32_t S, H, tiles_x, tiles_y, K;
   int32_t n_tiles;
   int64_t n;
@@ -59,11 +60,22 @@ struct BinParams {
   int32_t* flags;  // [0]: cap overflow
 };
 
+// floor(a / S) for |a| < 2^53: the double quotient is within one of it
+// (a is exact in double), then an exact integer correction.
+__device__ __forceinline__ int64_t floordiv_s(int64_t a, int32_t S, double invS) {
+  int64_t q = (int64_t)floor((double)a * invS);
+  if (q * S > a)
+    --q;
+  else if ((q + 1) * S <= a)
+    ++q;
+  return q;
+}
+
 // Visit every listed tile whose padded window contains point i.
 template <class F>
 __device__ __forceinline__ void for_each_window(const BinParams& p, int64_t i, F&& f) {
   const int64_t px = p.x[i], py = p.y[i];
-  const int64_t tx0 = ls_floordiv(px - p.ox, p.S), ty0 = ls_floordiv(py - p.oy, p.S);
+  const int64_t tx0 = floordiv_s(px - p.ox, p.S, p.invS), ty0 = floordiv_s(py - p.oy, p.S, p.invS);
   for (int64_t ty = ty0 - p.K; ty <= ty0 + p.K; ++ty) {
     if (ty < 0 || ty >= p.tiles_y) continue;
     const int64_t cy = p.oy + ty * p.S + p.S / 2;
@@ -112,6 +124,49 @@ __global__ void k_tile_pos_fix(int32_t* __restrict__ tile_pos, int64_t n_all) {
 __global__ void k_bin_count(BinParams p) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p.n; i += (int64_t)gridDim.x * blockDim.x)
     for_each_window(p, i, [&](int32_t s) { atomicAdd(&p.counts[s], 1); });
+}
+
+// Workgroup-private tile histograms: each workgroup bins a contiguous chunk
+// of points into an LDS histogram and adds it to the global counts with one
+// atomic per tile it touched (instead of one global atomic per membership on
+// a few hot counters).
+constexpr int BIN_THREADS = 1024;
+constexpr int BIN_LDS_TILES = 8192;
+
+__global__ void __launch_bounds__(BIN_THREADS) k_bin_count_lds(BinParams p, int64_t per_block) {
+  __shared__ int s_cnt[BIN_LDS_TILES];
+  for (int t = threadIdx.x; t < p.n_tiles; t += BIN_THREADS) s_cnt[t] = 0;
+  __syncthreads();
+  const int64_t i0 = blockIdx.x * per_block, i1 = min(p.n, i0 + per_block);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += BIN_THREADS)
+    for_each_window(p, i, [&](int32_t s) { atomicAdd(&s_cnt[s], 1); });
+  __syncthreads();
+  for (int t = threadIdx.x; t < p.n_tiles; t += BIN_THREADS)
+    if (s_cnt[t]) atomicAdd(&p.counts[t], s_cnt[t]);
+}
+
+// Scatter with the same chunks: local counts, one global reservation per
+// touched tile, then positions from LDS cursors.  Within a tile the order of
+// workgroups (and of lanes) is arbitrary; the per-tile sort restores
+// ascending order when the caller asks for the CSR.
+__global__ void __launch_bounds__(BIN_THREADS) k_bin_scatter_lds(BinParams p, int64_t per_block) {
+  __shared__ int s_cnt[BIN_LDS_TILES];
+  for (int t = threadIdx.x; t < p.n_tiles; t += BIN_THREADS) s_cnt[t] = 0;
+  __syncthreads();
+  const int64_t i0 = blockIdx.x * per_block, i1 = min(p.n, i0 + per_block);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += BIN_THREADS)
+    for_each_window(p, i, [&](int32_t s) { atomicAdd(&s_cnt[s], 1); });
+  __syncthreads();
+  for (int t = threadIdx.x; t < p.n_tiles; t += BIN_THREADS) {
+    const int c = s_cnt[t];
+    if (c) s_cnt[t] = p.bin_off[t] + atomicAdd(&p.fill[t], c);
+  }
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += BIN_THREADS)
+    for_each_window(p, i, [&](int32_t s) {
+      const int32_t pos = atomicAdd(&s_cnt[s], 1);
+      if (pos < p.cap) p.bin_idx[pos] = (int32_t)i;
+    });
 }
 
 // Single-workgroup exclusive scan of counts -> bin_off (n_tiles + 1 entries).
@@ -1072,6 +1127,7 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   BinParams bp;
   bp.ox = gi.ox;
   bp.oy = gi.oy;
+  bp.invS = 1.0 / gi.S;
   bp.S = gi.S;
   bp.H = gi.H;
   bp.tiles_x = gi.tx;
@@ -1089,9 +1145,18 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   bp.cap = cap;
   bp.flags = L.flags;
   const int pb = (int)std::min<int64_t>((n + T - 1) / T, 8192);
+  // workgroup-private histograms when the tile list fits in LDS
+  const bool lds_bins = n_tiles <= BIN_LDS_TILES;
+  const int64_t chunk = 4096;
+  const int nchunks = (int)std::max<int64_t>(1, (n + chunk - 1) / chunk);
   {
     LS_TRACE("bin_count", st);
-    if (n > 0) hipLaunchKernelGGL(k_bin_count, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
+    if (n > 0) {
+      if (lds_bins)
+        hipLaunchKernelGGL(k_bin_count_lds, dim3(nchunks), dim3(BIN_THREADS), 0, st, bp, chunk);
+      else
+        hipLaunchKernelGGL(k_bin_count, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
+    }
   }
   {
     LS_TRACE("bin_scan", st);
@@ -1099,7 +1164,12 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   }
   {
     LS_TRACE("bin_scatter", st);
-    if (n > 0) hipLaunchKernelGGL(k_bin_scatter, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
+    if (n > 0) {
+      if (lds_bins)
+        hipLaunchKernelGGL(k_bin_scatter_lds, dim3(nchunks), dim3(BIN_THREADS), 0, st, bp, chunk);
+      else
+        hipLaunchKernelGGL(k_bin_scatter, dim3(pb > 0 ? pb : 1), dim3(T), 0, st, bp);
+    }
   }
   if (user_csr)
     hipLaunchKernelGGL(k_bin_sort, dim3(std::min(n_tiles, 4 * num_cus())), dim3(RB), 0, st, boff, n_tiles, bidx,
