@@ -158,6 +158,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_conv_bf16(ConvArgsB A) {
 // pool also write the pooled 8 x 8 tile.
 constexpr int TT = 16;       // output tile side
 constexpr int PT = TT + 2;   // input patch side
+constexpr size_t LDS_MAX = 160 * 1024;  // LDS per workgroup on gfx950
 
 struct ConvTileArgs {
   ConvSrc src;
@@ -179,54 +180,12 @@ __host__ __device__ __forceinline__ int patch_pitch(int cin) {
   return 8 * (u + ((u & 1) ? 0 : 1));  // bf16 elements per pixel, odd number of 16-byte units
 }
 
+// Bias, ReLU and the store of one 16 x 16 output tile (and its 8 x 8 average
+// pool): the accumulators go through LDS so every lane stores whole 16-byte
+// channel groups.  All threads call it after the last MFMA.
 template <int NT>
-__global__ void __launch_bounds__(256) k_conv_bf16_lds(ConvTileArgs A) {
-  extern __shared__ __align__(16) unsigned char s_raw[];
-  uint16_t* s_in = reinterpret_cast<uint16_t*>(s_raw);
-  const int cin = A.src.a.c + A.src.b.c;
-  const int pitch = patch_pitch(cin);
-  const int per_img = A.tiles_x * A.tiles_y;
-  const int b = blockIdx.x / per_img;
-  const int t = blockIdx.x - b * per_img;
-  const int ty0 = (t / A.tiles_x) * TT, tx0 = (t % A.tiles_x) * TT;
-  const int iy0 = A.y0 + ty0 - 1, ix0 = A.x0 + tx0 - 1;
-  const int chunks = cin / 8;
-  for (int e = threadIdx.x; e < PT * PT * chunks; e += 256) {
-    const int pix = e / chunks, ch = e - pix * chunks;
-    const int py = pix / PT, px = pix - py * PT;
-    *reinterpret_cast<u16x8*>(s_in + pix * pitch + ch * 8) = load8(A.src, b, iy0 + py, ix0 + px, ch * 8, A.H, A.W);
-  }
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r16 = lane & 15, g = lane >> 4;
-  const int K = 9 * cin, KS = A.Kpad / 32;
-  f32x4 acc[4][NT];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int ks = 0; ks < KS; ++ks) {
-    const int k = ks * 32 + 8 * g;
-    bf16x8 bfr[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-      bfr[nt] = __builtin_bit_cast(bf16x8,
-                                   *reinterpret_cast<const u16x8*>(A.wp + (int64_t)(nt * 16 + r16) * A.Kpad + k));
-    const bool kv = k < K;
-    const int tap = kv ? k / cin : 0;
-    const int ci = k - tap * cin;
-    const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-    const uint16_t* base = s_in + ((wave * 4 + ky) * PT + r16 + kx) * pitch + ci;
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-      u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (kv) a = *reinterpret_cast<const u16x8*>(base + mt * PT * pitch);
-      const bf16x8 ab = __builtin_bit_cast(bf16x8, a);
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bfr[nt], acc[mt][nt], 0, 0, 0);
-    }
-  }
+__device__ __forceinline__ void conv_tile_store(const ConvTileArgs& A, f32x4 (&acc)[4][NT], int b, int ty0, int tx0,
+                                                int wave, int g, int r16, unsigned char* s_raw) {
   __syncthreads();  // the patch is dead; the same LDS now holds the output tile
   const int cout = A.cout;
   if (A.out_f32) {
@@ -291,6 +250,156 @@ __global__ void __launch_bounds__(256) k_conv_bf16_lds(ConvTileArgs A) {
       A.pool_out[(((int64_t)b * Hp + oy) * Wp + ox) * cout + c] = f2bf(0.25f * s);
     }
   }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_conv_bf16_lds(ConvTileArgs A) {
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  uint16_t* s_in = reinterpret_cast<uint16_t*>(s_raw);
+  const int cin = A.src.a.c + A.src.b.c;
+  const int pitch = patch_pitch(cin);
+  const int per_img = A.tiles_x * A.tiles_y;
+  const int b = blockIdx.x / per_img;
+  const int t = blockIdx.x - b * per_img;
+  const int ty0 = (t / A.tiles_x) * TT, tx0 = (t % A.tiles_x) * TT;
+  const int iy0 = A.y0 + ty0 - 1, ix0 = A.x0 + tx0 - 1;
+  const int chunks = cin / 8;
+  for (int e = threadIdx.x; e < PT * PT * chunks; e += 256) {
+    const int pix = e / chunks, ch = e - pix * chunks;
+    const int py = pix / PT, px = pix - py * PT;
+    *reinterpret_cast<u16x8*>(s_in + pix * pitch + ch * 8) = load8(A.src, b, iy0 + py, ix0 + px, ch * 8, A.H, A.W);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int K = 9 * cin, KS = A.Kpad / 32;
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = ks * 32 + 8 * g;
+    bf16x8 bfr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+      bfr[nt] = __builtin_bit_cast(bf16x8,
+                                   *reinterpret_cast<const u16x8*>(A.wp + (int64_t)(nt * 16 + r16) * A.Kpad + k));
+    const bool kv = k < K;
+    const int tap = kv ? k / cin : 0;
+    const int ci = k - tap * cin;
+    const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+    const uint16_t* base = s_in + ((wave * 4 + ky) * PT + r16 + kx) * pitch + ci;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (kv) a = *reinterpret_cast<const u16x8*>(base + mt * PT * pitch);
+      const bf16x8 ab = __builtin_bit_cast(bf16x8, a);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bfr[nt], acc[mt][nt], 0, 0, 0);
+    }
+  }
+  conv_tile_store<NT>(A, acc, b, ty0, tx0, wave, g, r16, s_raw);
+}
+
+constexpr int pitch_c(int cin) { return 8 * (cin / 8 + ((cin / 8) & 1 ? 0 : 1)); }
+
+// 8 consecutive FP32 values rounded to BF16 bits.
+__device__ __forceinline__ u16x8 f32x8_to_bf16(const float* p) {
+  const float4 f0 = *reinterpret_cast<const float4*>(p);
+  const float4 f1 = *reinterpret_cast<const float4*>(p + 4);
+  u16x8 r;
+  r[0] = f2bf(f0.x);
+  r[1] = f2bf(f0.y);
+  r[2] = f2bf(f0.z);
+  r[3] = f2bf(f0.w);
+  r[4] = f2bf(f1.x);
+  r[5] = f2bf(f1.y);
+  r[6] = f2bf(f1.z);
+  r[7] = f2bf(f1.w);
+  return r;
+}
+
+// The channels of one stored part at input-plane pixel (yy, xx) into LDS
+// (zeros outside the plane or the part), C channels, 16 bytes at a time.
+template <int C, bool UP, bool F32>
+__device__ __forceinline__ void load_part(const SrcPart& p, int b, int yy, int xx, bool in_plane, uint16_t* dst) {
+  int sy, sx;
+  if (UP) {
+    sy = yy >> 1;
+    sx = xx >> 1;
+  } else {
+    sy = yy - p.oy;
+    sx = xx - p.ox;
+  }
+  const bool ok = in_plane && sy >= 0 && sx >= 0 && sy < p.h && sx < p.w;
+  const int64_t o = (((int64_t)b * p.h + sy) * p.w + sx) * p.stride + p.coff;
+#pragma unroll
+  for (int c = 0; c < C / 8; ++c) {
+    u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (ok) v = F32 ? f32x8_to_bf16(p.f32 + o + 8 * c) : *reinterpret_cast<const u16x8*>(p.bf16 + o + 8 * c);
+    *reinterpret_cast<u16x8*>(dst + 8 * c) = v;
+  }
+}
+
+// k_conv_bf16_lds specialised at compile time on the layer's input: CA
+// channels from part a (nearest-upsampled if UPA, FP32-stored if F32A) and
+// CB from part b.  Patch coordinates are computed once per pixel, the K loop
+// is unrolled with the tap and channel of every step known up to the lane's
+// 8-channel group, and the MFMA sequence per output is the generic kernel's
+// (identical results).
+template <int NT, int CA, int CB, bool UPA, bool F32A, bool F32B>
+__global__ void __launch_bounds__(256) k_conv_bf16_lds_t(ConvTileArgs A) {
+  constexpr int CIN = CA + CB, PITCH = pitch_c(CIN), K = 9 * CIN, KS = (K + 31) / 32, KPAD = KS * 32;
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  uint16_t* s_in = reinterpret_cast<uint16_t*>(s_raw);
+  const int per_img = A.tiles_x * A.tiles_y;
+  const int b = blockIdx.x / per_img;
+  const int t = blockIdx.x - b * per_img;
+  const int ty0 = (t / A.tiles_x) * TT, tx0 = (t % A.tiles_x) * TT;
+  const int iy0 = A.y0 + ty0 - 1, ix0 = A.x0 + tx0 - 1;
+  for (int pix = threadIdx.x; pix < PT * PT; pix += 256) {
+    const int py = pix / PT, px = pix - py * PT;
+    const int yy = iy0 + py, xx = ix0 + px;
+    const bool in_plane = yy >= 0 && xx >= 0 && yy < A.H && xx < A.W;
+    uint16_t* dst = s_in + pix * PITCH;
+    load_part<CA, UPA, F32A>(A.src.a, b, yy, xx, in_plane, dst);
+    if (CB > 0) load_part<CB, false, F32B>(A.src.b, b, yy, xx, in_plane, dst + CA);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* wrow = A.wp + (int64_t)r16 * KPAD + 8 * g;
+  const uint16_t* base = s_in + (wave * 4 * PT + r16) * PITCH;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = ks * 32 + 8 * g;
+    bf16x8 bfr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+      bfr[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(wrow + nt * 16 * KPAD + ks * 32));
+    const bool kv = k < K;
+    const int tap = kv ? k / CIN : 0;
+    const int ci = k - tap * CIN;
+    const int ky = tap / 3, kx = tap - 3 * ky;
+    const uint16_t* pb = base + (ky * PT + kx) * PITCH + ci;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (kv) a = *reinterpret_cast<const u16x8*>(pb + mt * PT * PITCH);
+      const bf16x8 ab = __builtin_bit_cast(bf16x8, a);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bfr[nt], acc[mt][nt], 0, 0, 0);
+    }
+  }
+  conv_tile_store<NT>(A, acc, b, ty0, tx0, wave, g, r16, s_raw);
 }
 
 __global__ void k_avgpool_bf16(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int B, int H, int W, int C) {
@@ -542,10 +651,50 @@ int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed,
   const dim3 grid((unsigned)(B * a.tiles_x * a.tiles_y));
   const int nt = (a.cout + 15) / 16;
   LS_TRACE("conv_bf16", st);
+  // the layer's own specialisation when the sources are the network's
+  auto is = [&](int ca, int cb, bool upa, bool f32a, bool f32b) {
+    return s.a.c == ca && s.b.c == cb && (s.a.up != 0) == upa && (s.a.f32 != nullptr) == f32a &&
+           (cb == 0 || ((s.b.f32 != nullptr) == f32b && !s.b.up));
+  };
+#define LS_SPEC(L, N, CA, CB, UPA, F32A, F32B)                                                          \
+  if (l == L && nt == N && is(CA, CB, UPA, F32A, F32B)) {                                            \
+    if (lds > 65536)                                                                                 \
+      LS_HOST_CHECK(hipFuncSetAttribute(                                                             \
+          reinterpret_cast<const void*>(&k_conv_bf16_lds_t<N, CA, CB, UPA, F32A, F32B>),             \
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                                    \
+    hipLaunchKernelGGL((k_conv_bf16_lds_t<N, CA, CB, UPA, F32A, F32B>), grid, dim3(256), lds, st, a); \
+    LS_LAUNCH_CHECK();                                                                               \
+    return LS_OK;                                                                                    \
+  }
+  LS_SPEC(0, 1, 8, 0, false, true, false)
+  LS_SPEC(1, 1, 16, 0, false, false, false)
+  LS_SPEC(2, 2, 16, 0, false, false, false)
+  LS_SPEC(3, 2, 32, 0, false, false, false)
+  LS_SPEC(4, 4, 32, 0, false, false, false)
+  LS_SPEC(5, 4, 64, 0, false, false, false)
+  LS_SPEC(6, 2, 64, 32, true, false, false)
+  LS_SPEC(7, 2, 32, 0, false, false, false)
+  LS_SPEC(8, 1, 32, 16, true, false, false)
+  LS_SPEC(9, 1, 16, 0, false, false, false)
+  LS_SPEC(10, 1, 16, 8, false, false, true)
+#undef LS_SPEC
+  auto generic = [&](const void* f) -> int {
+    if (lds > 65536) LS_HOST_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    return LS_OK;
+  };
   switch (nt) {
-    case 1: hipLaunchKernelGGL(k_conv_bf16_lds<1>, grid, dim3(256), lds, st, a); break;
-    case 2: hipLaunchKernelGGL(k_conv_bf16_lds<2>, grid, dim3(256), lds, st, a); break;
-    case 4: hipLaunchKernelGGL(k_conv_bf16_lds<4>, grid, dim3(256), lds, st, a); break;
+    case 1:
+      if (generic(reinterpret_cast<const void*>(&k_conv_bf16_lds<1>)) != LS_OK) return LS_EHIP;
+      hipLaunchKernelGGL(k_conv_bf16_lds<1>, grid, dim3(256), lds, st, a);
+      break;
+    case 2:
+      if (generic(reinterpret_cast<const void*>(&k_conv_bf16_lds<2>)) != LS_OK) return LS_EHIP;
+      hipLaunchKernelGGL(k_conv_bf16_lds<2>, grid, dim3(256), lds, st, a);
+      break;
+    case 4:
+      if (generic(reinterpret_cast<const void*>(&k_conv_bf16_lds<4>)) != LS_OK) return LS_EHIP;
+      hipLaunchKernelGGL(k_conv_bf16_lds<4>, grid, dim3(256), lds, st, a);
+      break;
     default: return LS_ENOTIMPL;
   }
   LS_LAUNCH_CHECK();
@@ -614,7 +763,7 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   // a layer feeding an average pool writes the pooled tensor too when it uses the LDS tile
   auto conv = [&](const ConvSrc& s, int H, int l, uint16_t* out, uint16_t* pooled) -> int {
     const int cin_l = LS_LAYERS[l].cin;
-    if (variant(l) == 1 && (size_t)PT * PT * patch_pitch(cin_l) * 2 <= 65536) {
+    if (variant(l) == 1 && (size_t)PT * PT * patch_pitch(cin_l) * 2 <= LDS_MAX) {
       const bool fuse = pooled && H % TT == 0;
       LS_TRYB(conv_bf16_lds(s, B, H, l, packed, w, out, nullptr, fuse ? pooled : nullptr, 1, 0, 0, H, H, st));
       if (pooled && !fuse) return pool_bf16(out, pooled, B, H, LS_LAYERS[l].cout, st);
@@ -638,7 +787,7 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   LS_TRYB(conv(cs(bpart(A7, 32, R2), none), R2, 7, A8, nullptr));
   LS_TRYB(conv(cs(u8, bpart(A2, 16, R)), R, 8, A9, nullptr));
   LS_TRYB(conv(cs(bpart(A9, 16, R), none), R, 9, A10, nullptr));
-  if (variant(10) == 1 && (size_t)PT * PT * patch_pitch(24) * 2 <= 65536)
+  if (variant(10) == 1 && (size_t)PT * PT * patch_pitch(24) * 2 <= LDS_MAX)
     return conv_bf16_lds(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,
                          gi.res, gi.res, st);
   return conv_bf16(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, 0, gi.pad, gi.pad, gi.res, gi.res,
