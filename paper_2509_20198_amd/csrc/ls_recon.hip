@@ -464,7 +464,8 @@ __device__ int third_left(const Tile& T, int a, int b) {
         hy1 = fmax(hy1, py[i]);
       }
       if ((oi > 0.0 && oj < 0.0) || (oi < 0.0 && oj > 0.0)) {
-        const double t = oi / (oi - oj);
+        // crossing point in float (error far below the slack added below)
+        const double t = (double)((float)oi * __builtin_amdgcn_rcpf((float)(oi - oj)));
         const double qx = px[i] + t * (px[j] - px[i]), qy = py[i] + t * (py[j] - py[i]);
         hx0 = fmin(hx0, qx);
         hx1 = fmax(hx1, qx);
@@ -479,18 +480,63 @@ __device__ int third_left(const Tile& T, int a, int b) {
   int rmax = max(max(bx0 - bb.x0, bb.x1 - bx0), max(by0 - bb.y0, bb.y1 - by0));
   int best = -1;
   int2 C = make_int2(0, 0);
-  double ocx = 0.0, ocy = 0.0, rho = 0.0;  // circle centre (tile-local) and radius
+  // Circle through a, b and the best point as of the last geometry update.
+  // Circles through a and b are nested on the left of the line (a point
+  // inside one lies inside every circle whose centre is farther left), and
+  // every improvement moves the centre right, so the possibly stale circle
+  // stays a conservative filter; the exact in-circle test decides.
+  double ocx = 0.0, ocy = 0.0;
+  double lim2 = 0.0;  // squared reach of that circle, with margin
+  bool have_circle = false, dirty = false;
   // orient(a, b, .) is linear with gradient (-fby, fbx): over a rectangle it
   // peaks at the corner these signs pick
   const bool hi_x = fby <= 0.0, hi_y = fbx >= 0.0;
   const double inv_ll = 1.0 / sqrt(bl);
-  double lim2 = 0.0;  // squared reach of the current circle, with margin
+  auto update_circle = [&]() {
+    // circumcircle of (a, b, best) relative to a
+    const double cx = C.x - ax, cy = C.y - ay;
+    const double cl = cx * cx + cy * cy;
+    const double iD = 0.5 / (fbx * cy - fby * cx);
+    const double ox = (cy * bl - fby * cl) * iD, oy = (fbx * cl - cx * bl) * iD;
+    const double rho = sqrt(ox * ox + oy * oy);
+    ocx = ox + ax;
+    ocy = oy + ay;
+    {
+      const double lim = rho * (1.0 + 1e-9) + 2.0;
+      lim2 = lim * lim;
+    }
+    // signed distance of the centre from the line, > 0 on the left
+    const double dc = (fbx * oy - fby * ox) * inv_ll;
+    double cx0, cx1, cy0, cy1;
+    if (dc <= 0.0) {
+      // sagitta rho - |dc| = (|ab|/2)^2 / (rho + |dc|), free of cancellation
+      const double h = bl / (4.0 * (rho - dc)) * (1.0 + 1e-9);
+      const double nx = -fby * inv_ll * h, ny = fbx * inv_ll * h;
+      cx0 = fmin(fmin(ax, bx), fmin(ax + nx, bx + nx));
+      cx1 = fmax(fmax(ax, bx), fmax(ax + nx, bx + nx));
+      cy0 = fmin(fmin(ay, by), fmin(ay + ny, by + ny));
+      cy1 = fmax(fmax(ay, by), fmax(ay + ny, by + ny));
+    } else {
+      cx0 = ocx - rho;
+      cx1 = ocx + rho;
+      cy0 = ocy - rho;
+      cy1 = ocy + rho;
+    }
+    const BucketBox cb = bucket_box(T, cx0, cx1, cy0, cy1, 2.0 + rho * 1e-9);
+    bb.x0 = max(half.x0, cb.x0);
+    bb.x1 = min(half.x1, cb.x1);
+    bb.y0 = max(half.y0, cb.y0);
+    bb.y1 = min(half.y1, cb.y1);
+    rmax = max(max(bx0 - bb.x0, bb.x1 - bx0), max(by0 - bb.y0, bb.y1 - by0));
+    have_circle = true;
+    dirty = false;
+  };
   auto visit = [&](int qx, int qy) {
     // bucket rectangle in tile-local coordinates, rounded outwards to integers
     const double x0 = floor(qx * T.bw) - T.H - 1.0, x1 = ceil((qx + 1) * T.bw) - T.H + 1.0;
     const double y0 = floor(qy * T.bw) - T.H - 1.0, y1 = ceil((qy + 1) * T.bw) - T.H + 1.0;
     if (orient_d(ax, ay, bx, by, hi_x ? x1 : x0, hi_y ? y1 : y0) <= 0.0) return;
-    if (best >= 0) {
+    if (have_circle) {
       const double dx = fmax(fmax(x0 - ocx, ocx - x1), 0.0), dy = fmax(fmax(y0 - ocy, ocy - y1), 0.0);
       if (dx * dx + dy * dy > lim2) return;
     }
@@ -501,49 +547,17 @@ __device__ int third_left(const Tile& T, int a, int b) {
       const int2 P = T.uv[p];
       if (orient_d(ax, ay, bx, by, P.x, P.y) <= 0.0) continue;
       if (best >= 0) {
-        // clearly outside the current circle: no need for the exact test (the
-        // margin covers the rounding of the centre and radius)
-        const double ex = P.x - ocx, ey = P.y - ocy;
-        if (ex * ex + ey * ey > lim2) continue;
+        // clearly outside the circle: no need for the exact test (the margin
+        // covers the rounding of the centre and radius)
+        if (have_circle) {
+          const double ex = P.x - ocx, ey = P.y - ocy;
+          if (ex * ex + ey * ey > lim2) continue;
+        }
         if (incircle_sos(a, b, best, p, A, B, C, P) <= 0) continue;
       }
       best = p;
       C = P;
-      // circumcircle of (a, b, p) relative to a
-      const double cx = P.x - ax, cy = P.y - ay;
-      const double cl = cx * cx + cy * cy;
-      const double iD = 0.5 / (fbx * cy - fby * cx);
-      const double ox = (cy * bl - fby * cl) * iD, oy = (fbx * cl - cx * bl) * iD;
-      rho = sqrt(ox * ox + oy * oy);
-      ocx = ox + ax;
-      ocy = oy + ay;
-      {
-        const double lim = rho * (1.0 + 1e-9) + 2.0;
-        lim2 = lim * lim;
-      }
-      // signed distance of the centre from the line, > 0 on the left
-      const double dc = (fbx * oy - fby * ox) * inv_ll;
-      double cx0, cx1, cy0, cy1;
-      if (dc <= 0.0) {
-        // sagitta rho - |dc| = (|ab|/2)^2 / (rho + |dc|), free of cancellation
-        const double h = bl / (4.0 * (rho - dc)) * (1.0 + 1e-9);
-        const double nx = -fby * inv_ll * h, ny = fbx * inv_ll * h;
-        cx0 = fmin(fmin(ax, bx), fmin(ax + nx, bx + nx));
-        cx1 = fmax(fmax(ax, bx), fmax(ax + nx, bx + nx));
-        cy0 = fmin(fmin(ay, by), fmin(ay + ny, by + ny));
-        cy1 = fmax(fmax(ay, by), fmax(ay + ny, by + ny));
-      } else {
-        cx0 = ocx - rho;
-        cx1 = ocx + rho;
-        cy0 = ocy - rho;
-        cy1 = ocy + rho;
-      }
-      const BucketBox cb = bucket_box(T, cx0, cx1, cy0, cy1, 2.0 + rho * 1e-9);
-      bb.x0 = max(half.x0, cb.x0);
-      bb.x1 = min(half.x1, cb.x1);
-      bb.y0 = max(half.y0, cb.y0);
-      bb.y1 = min(half.y1, cb.y1);
-      rmax = max(max(bx0 - bb.x0, bb.x1 - bx0), max(by0 - bb.y0, bb.y1 - by0));
+      dirty = true;
     }
   };
   for (int r = 0; r <= rmax; ++r) {
@@ -576,6 +590,7 @@ __device__ int third_left(const Tile& T, int a, int b) {
       }
       visit(cx, cy);
     }
+    if (dirty) update_circle();
   }
   return best;
 }
