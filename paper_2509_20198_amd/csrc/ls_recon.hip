@@ -366,7 +366,7 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
   const int bx0 = bucket_1d(qx + T.H, G, T.W2), by0 = bucket_1d(qy + T.H, G, T.W2);
   const double fx = qx + T.H, fy = qy + T.H;  // grid-local
   int best = -1;
-  int64_t bd = 0;
+  double bd = 0.0;  // squared distance, exact in double (below 2^36)
   int bu = 0, bv = 0;
   for (int r = 0;; ++r) {
     const int ylo = by0 - r, yhi = by0 + r, xlo = bx0 - r, xhi = bx0 + r;
@@ -380,15 +380,15 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
           const double x0 = floor(bx * T.bw) - 1.0, x1 = ceil((bx + 1) * T.bw) + 1.0;
           const double y0 = floor(by * T.bw) - 1.0, y1 = ceil((by + 1) * T.bw) + 1.0;
           const double dx = fmax(fmax(x0 - fx, fx - x1), 0.0), dy = fmax(fmax(y0 - fy, fy - y1), 0.0);
-          if (dx * dx + dy * dy > (double)bd) continue;
+          if (dx * dx + dy * dy > bd) continue;
         }
         const int b = by * G + bx;
         const int e = T.boff[b + 1];
         for (int p = T.boff[b]; p < e; ++p) {
           if (p == skip) continue;
           const int2 q = T.uv[p];
-          const int64_t dx = q.x - qx, dy = q.y - qy;
-          const int64_t d = dx * dx + dy * dy;
+          const double dx = q.x - qx, dy = q.y - qy;
+          const double d = fma(dx, dx, dy * dy);
           if (best < 0 || d < bd || (d == bd && (q.y < bv || (q.y == bv && q.x < bu)))) {
             best = p;
             bd = d;
@@ -403,7 +403,7 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
       const double L = fmin(fmin(fx - floor((bx0 - r) * T.bw), ceil((bx0 + r + 1) * T.bw) - fx),
                             fmin(fy - floor((by0 - r) * T.bw), ceil((by0 + r + 1) * T.bw) - fy)) -
                        1.0;
-      if (L > 0.0 && (double)bd < L * L) break;
+      if (L > 0.0 && bd < L * L) break;
     }
     if (ring_covers_grid(T, bx0, by0, r)) break;
   }
