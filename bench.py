@@ -305,17 +305,20 @@ def bench_splat(n_points: int, dev):
     nd = torch.zeros(1, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     fn = lambda: ls.splat_points(g, x, y, z, rgb, ts, nslots, keys=keys, n_dropped=nd)  # noqa: E731
-    fn()
+    for _ in range(3):
+        fn()
     torch.cuda.synchronize()
     ls.trace_enable(True)
-    reps = 5
+    reps = 10
     for _ in range(reps):
         fn()
     torch.cuda.synchronize()
-    ms = sum(t for n, t in ls.trace_records() if n == "splat") / reps
+    times = sorted(t for n, t in ls.trace_records() if n == "splat")
     ls.trace_enable(False)
+    ms = times[len(times) // 2]  # median launch
     alg_bytes = n_points * 18 + nslots * 64 * 64 * 8
-    return {"workload": f"{n_points} points, 64x64 tiles, Morton-ordered", "ms": ms,
+    return {"workload": f"{n_points} points, 64x64 tiles, Morton-ordered", "ms": ms, "ms_min": times[0],
+            "ms_mean": sum(times) / len(times),
             "points_per_s": n_points / (ms * 1e-3), "algorithmic_GBps": alg_bytes / (ms * 1e-3) / 1e9,
             "frac_hbm_peak": alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
 

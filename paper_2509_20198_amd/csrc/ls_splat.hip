@@ -186,7 +186,8 @@ __device__ __forceinline__ uint32_t splat_colour(const SplatRegs& r, int s, int 
   return (v & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
-// One workgroup per batch of SPLAT_BATCH consecutive points (grid-stride).
+// One workgroup per batch of SPLAT_BATCH consecutive points (grid-stride, so
+// any grid size is correct).
 // When the batch's texels span fewer than SPLAT_WIN Morton codes, keys are
 // first max-reduced in an LDS window indexed by Morton code and flushed with
 // one global 64-bit atomic max per touched texel; otherwise every point
@@ -303,19 +304,6 @@ __global__ void k_resolve(const unsigned long long* __restrict__ keys, int64_t n
   }
 }
 
-int g_cus = 0;
-int cus() {
-  if (g_cus <= 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      g_cus = v;
-    else
-      g_cus = 256;
-  }
-  return g_cus;
-}
-
 }  // namespace
 
 int ls_resolve_impl(const LsGridInfo& gi, const uint64_t* keys, int32_t n_slots, float* tex_inout, hipStream_t st) {
@@ -359,7 +347,9 @@ int ls_splat_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   p.n_dropped = reinterpret_cast<unsigned long long*>(n_dropped);
   if (n > 0) {
     const int64_t batches = (n + SPLAT_BATCH - 1) / SPLAT_BATCH;
-    const int blocks = (int)std::min<int64_t>(batches, 8 * cus());
+    // one workgroup per batch: finished workgroups are replaced at once,
+    // which balances better than a persistent grid (measured)
+    const int blocks = (int)std::min<int64_t>(batches, 0x7fffffff);
     LS_TRACE("splat", st);
     hipLaunchKernelGGL(k_splat, dim3(blocks), dim3(SPLAT_THREADS), 0, st, p);
     LS_LAUNCH_CHECK();
