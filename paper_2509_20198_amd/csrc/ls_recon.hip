@@ -7,8 +7,10 @@
 //      listed tile's padded window [c - H, c + H)^2 (a point sits in 1, 2 or
 //      4 windows with the paper's 16-texel ring).
 //   3. k_bin_sort (only when the caller asks for the CSR): ascending order.
-//   4. k_recon: persistent, one workgroup per tile popped from a queue in
-//      tile_list order.  Phases, separated by barriers:
+//   4. k_recon: persistent, one workgroup per tile popped from a queue that
+//      holds the tiles by descending window point count (longest first, so
+//      the last tiles to start are short and the workgroups finish
+//      together).  Phases, separated by barriers:
 //        a. gather the tile's points to tile-local coordinates and bucket
 //           them into a G x G grid over the window (LDS counting sort);
 //        b. sort each bucket by (v, u) and drop duplicate positions,
@@ -58,6 +60,7 @@ struct BinParams {
   int32_t* bin_idx;
   int64_t cap;
   int32_t* flags;  // [0]: cap overflow
+  int32_t* order;  // recon processing order (tile slots)
 };
 
 // floor(a / S) for |a| < 2^53: the double quotient is within one of it
@@ -169,10 +172,21 @@ __global__ void __launch_bounds__(BIN_THREADS) k_bin_scatter_lds(BinParams p, in
     });
 }
 
-// Single-workgroup exclusive scan of counts -> bin_off (n_tiles + 1 entries).
+constexpr int ORDER_KEYS = 4096;
+
+// Descending window count, in steps of 4 points, as an ascending key.
+__device__ __forceinline__ int order_key(int32_t count) {
+  return ORDER_KEYS - 1 - min(max(count, 0) >> 2, ORDER_KEYS - 1);
+}
+
+// Single-workgroup exclusive scan of counts -> bin_off (n_tiles + 1 entries),
+// then the recon processing order: a counting sort of the tile slots by
+// order_key (slots with equal keys in any order; the results do not depend
+// on the order).
 __global__ void __launch_bounds__(1024) k_bin_scan(BinParams p) {
   __shared__ int64_t s_part[1024];
   __shared__ int64_t s_carry;
+  __shared__ int s_hist[ORDER_KEYS];
   const int tid = threadIdx.x;
   if (tid == 0) s_carry = 0;
   __syncthreads();
@@ -198,6 +212,29 @@ __global__ void __launch_bounds__(1024) k_bin_scan(BinParams p) {
     p.bin_off[p.n_tiles] = (int32_t)(total < 0x7fffffff ? total : 0x7fffffff);
     p.flags[0] = total > p.cap ? 1 : 0;
   }
+  constexpr int PER = ORDER_KEYS / 1024;
+  for (int b = tid; b < ORDER_KEYS; b += 1024) s_hist[b] = 0;
+  __syncthreads();
+  for (int i = tid; i < p.n_tiles; i += 1024) atomicAdd(&s_hist[order_key(p.counts[i])], 1);
+  __syncthreads();
+  int run = 0;
+  for (int j = 0; j < PER; ++j) run += s_hist[tid * PER + j];
+  s_part[tid] = run;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t t = tid >= o ? s_part[tid - o] : 0;
+    __syncthreads();
+    s_part[tid] += t;
+    __syncthreads();
+  }
+  int excl = (int)(s_part[tid] - run);
+  for (int j = 0; j < PER; ++j) {
+    const int c = s_hist[tid * PER + j];
+    s_hist[tid * PER + j] = excl;
+    excl += c;
+  }
+  __syncthreads();
+  for (int i = tid; i < p.n_tiles; i += 1024) p.order[atomicAdd(&s_hist[order_key(p.counts[i])], 1)] = i;
 }
 
 __global__ void k_bin_scatter(BinParams p) {
@@ -278,6 +315,7 @@ struct ReconParams {
   uint64_t* facemap;  // [gridDim][R*R]
   int32_t* nnidx;     // [gridDim][R*R]
   int32_t* queue;
+  const int32_t* order;  // queue position -> tile slot
   float* x_out;
   double* cz_out;
   int32_t* status;
@@ -791,7 +829,8 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
   // let the compiler re-enter the barriers without the queue fetch).
   for (;;) {
     if (tid == 0) {
-      const int kk = atomicAdd(P.queue, 1);
+      const int q = atomicAdd(P.queue, 1);
+      const int kk = q < P.n_tiles ? P.order[q] : q;
       s_hdr[0] = kk;
       if (kk < P.n_tiles) {
         int f = cap_overflow ? LS_TILE_CAP : 0;
@@ -1049,6 +1088,7 @@ struct ReconLayout {
   int32_t* fill;
   int32_t* flags;
   int32_t* queue;
+  int32_t* order;
   int32_t* bin_off;
   int32_t* bin_idx;
   int32_t* sort_scratch;
@@ -1082,6 +1122,7 @@ size_t recon_layout(const LsGridInfo& gi, int32_t n_tiles, int64_t n, void* base
   L->fill = A.take<int32_t>(n_tiles + 1);
   L->flags = A.take<int32_t>(4);
   L->queue = L->flags + 1;
+  L->order = A.take<int32_t>(n_tiles);
   L->bin_off = A.take<int32_t>(n_tiles + 1);
   L->bin_idx = A.take<int32_t>(E);
   L->sort_scratch = A.take<int32_t>(2 * E);
@@ -1159,6 +1200,7 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   bp.bin_idx = bidx;
   bp.cap = cap;
   bp.flags = L.flags;
+  bp.order = L.order;
   const int pb = (int)std::min<int64_t>((n + T - 1) / T, 8192);
   // workgroup-private histograms when the tile list fits in LDS
   const bool lds_bins = n_tiles <= BIN_LDS_TILES;
@@ -1224,6 +1266,7 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   rp.facemap = L.facemap;
   rp.nnidx = L.nnidx;
   rp.queue = L.queue;
+  rp.order = L.order;
   rp.x_out = x_out;
   rp.cz_out = cz_out;
   rp.status = tile_status;

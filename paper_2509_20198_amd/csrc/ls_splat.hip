@@ -12,7 +12,7 @@
 // chunks), the batch is first reduced in LDS with 64-bit max (one slot per
 // Morton code) and then flushed with one global 64-bit atomic max per
 // touched texel; otherwise every point goes straight to a global atomic max.
-// The small window (8 KB) and 60 VGPRs let eight waves per SIMD share a CU,
+// The small window (16 KB) lets several workgroups share a CU,
 // so the loads of some overlap the LDS phases of others.
 #include <algorithm>
 
@@ -22,10 +22,10 @@ namespace {
 
 constexpr int SPLAT_THREADS = 256;
 #ifndef LS_SPLAT_PPT
-#define LS_SPLAT_PPT 4
+#define LS_SPLAT_PPT 8
 #endif
 #ifndef LS_SPLAT_WIN
-#define LS_SPLAT_WIN 1024
+#define LS_SPLAT_WIN 2048
 #endif
 constexpr int SPLAT_PPT = LS_SPLAT_PPT;                 // points per thread per batch (multiple of 4)
 constexpr int SPLAT_QPT = SPLAT_PPT / 4;                // point quads per thread per batch
