@@ -311,6 +311,7 @@ struct ReconParams {
   int32_t* tz;
   uint64_t* trgb;
   int2* cuv;
+  uint64_t* tris;  // 2 entries per bin entry: large triangles of a tile, rasterised after its stars
   // per workgroup scratch
   uint64_t* facemap;  // [gridDim][R*R]
   int32_t* nnidx;     // [gridDim][R*R]
@@ -727,6 +728,44 @@ __device__ void raster_triangle(const Tile& T, int a, int b, int c, int C, int R
   }
 }
 
+// Texel bounding box of triangle (a, b, c); false when it holds no texel.
+__device__ __forceinline__ bool tri_texel_box(const Tile& T, int a, int b, int c, int C, int R, int& i0, int& i1,
+                                              int& j0, int& j1) {
+  const int2 A = T.uv[a], B = T.uv[b], Cc = T.uv[c];
+  texel_range(min(A.x, min(B.x, Cc.x)), max(A.x, max(B.x, Cc.x)), T.H, C, R, j0, j1);
+  texel_range(min(A.y, min(B.y, Cc.y)), max(A.y, max(B.y, Cc.y)), T.H, C, R, i0, i1);
+  return i0 <= i1 && j0 <= j1;
+}
+
+// Triangles whose texel box exceeds this many texels are rasterised after
+// the star phase by a whole wave (one lane per texel of the box), so a few
+// large triangles do not hold up the lanes of a wave that walk their stars.
+constexpr int WAVE_RASTER_TEXELS = 24;
+
+// raster_triangle's result, computed by the 64 lanes of a wave: every texel
+// of the box gets the exact top-left test.
+__device__ void raster_triangle_wave(const Tile& T, uint64_t key, int C, int R, uint64_t* __restrict__ fm, int lane) {
+  const int a = (int)(key >> 42), b = (int)((key >> 21) & 0x1FFFFF), c = (int)(key & 0x1FFFFF);
+  int i0, i1, j0, j1;
+  if (!tri_texel_box(T, a, b, c, C, R, i0, i1, j0, j1)) return;
+  const int2 A = T.uv[a], B = T.uv[b], Cc = T.uv[c];
+  const int ax = A.x, ay = A.y, bx = B.x, by = B.y, cx = Cc.x, cy = Cc.y;
+  const bool oa = edge_owned(bx, by, cx, cy), ob = edge_owned(cx, cy, ax, ay), oc = edge_owned(ax, ay, bx, by);
+  const int q0 = -T.H + C / 2;
+  const int w = j1 - j0 + 1, n = (i1 - i0 + 1) * w;
+  const float rw = __builtin_amdgcn_rcpf((float)w);
+  for (int e = lane; e < n; e += 64) {
+    // e / w from a float estimate (e < 2^14), corrected exactly
+    int di = (int)((float)e * rw);
+    if (di * w > e)
+      --di;
+    else if ((di + 1) * w <= e)
+      ++di;
+    const int i = i0 + di, j = j0 + (e - di * w);
+    if (tri_inside(ax, ay, bx, by, cx, cy, oa, ob, oc, q0 + j * C, q0 + i * C)) fm[i * R + j] = key;
+  }
+}
+
 // Texels lying exactly on hull edge a->b get the triangle next to it.  Per
 // texel row the line crosses at most one texel centre, found exactly in
 // integers.
@@ -815,6 +854,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
   __shared__ int s_tmp[RB / 64 + 1];
   __shared__ int s_hdr[5];  // tile index, flags, bin offset, bin count, tile id
   __shared__ int s_flags;
+  __shared__ int s_ntri;
   __shared__ double s_cz;
   const int tid = threadIdx.x;
   const int R = P.R, C = P.C, H = P.H, W2 = 2 * P.H;
@@ -869,7 +909,10 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       const bool uv_lds = 2 * cnt <= LDS_INTS - (NB + 1);
       // ---- a. gather + bucket histogram
       for (int b = tid; b <= NB; b += RB) s_b[b] = 0;
-      if (tid == 0) s_flags = 0;
+      if (tid == 0) {
+        s_flags = 0;
+        s_ntri = 0;
+      }
       __syncthreads();
       for (int e = tid; e < cnt; e += RB) {
         const int32_t gi = P.bin_idx[off + e];
@@ -966,6 +1009,22 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       const bool has_dt = (__builtin_amdgcn_readfirstlane(__syncthreads_or(noncol)) != 0) && m < (1 << 21);
       if (m >= (1 << 21) && tid == 0) atomicOr(&s_flags, LS_TILE_DEGENERATE);
       // ---- d. Delaunay stars, rasterised into the face map
+      uint64_t* __restrict__ tris = P.tris + 2 * (int64_t)off;
+      // a small triangle is rasterised by its lane at once, a large one is
+      // queued for the wave pass below (or rasterised at once if the queue,
+      // sized for the 2m - 5 triangles of a triangulation, is full)
+      auto emit = [&](int p, int q, int r) {
+        int i0, i1, j0, j1;
+        if (!tri_texel_box(T, p, q, r, C, R, i0, i1, j0, j1)) return;
+        if ((i1 - i0 + 1) * (j1 - j0 + 1) > WAVE_RASTER_TEXELS) {
+          const int slot = atomicAdd(&s_ntri, 1);
+          if (slot < 2 * cnt) {
+            tris[slot] = face_key(p, q, r);
+            return;
+          }
+        }
+        raster_triangle(T, p, q, r, C, R, fm);
+      };
       if (has_dt) {
         for (int a = tid; a < m; a += RB) {
           const int b0 = ring_nearest(T, T.uv[a].x, T.uv[a].y, a);
@@ -982,7 +1041,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
               if (prev_b >= 0) hull_key = face_key(a, prev_b, b);
               break;
             }
-            if (a < b && a < c) raster_triangle(T, a, b, c, C, R, fm);
+            if (a < b && a < c) emit(a, b, c);
             prev_b = b;
             b = c;
             if (b == b0) {
@@ -998,13 +1057,18 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
               if (c < 0) break;
               if (first && hull_key == FACE_NONE) hull_key = face_key(b, a, c);
               first = false;
-              if (a < b && a < c) raster_triangle(T, b, a, c, C, R, fm);
+              if (a < b && a < c) emit(b, a, c);
               b = c;
             }
           }
           if (steps > STAR_MAX_STEPS) atomicOr(&s_flags, LS_TILE_DEGENERATE);
           if (hull_b >= 0 && hull_key != FACE_NONE) raster_hull_edge(T, a, hull_b, hull_key, C, R, fm);
         }
+      }
+      __syncthreads();
+      {
+        const int ntri = min(__builtin_amdgcn_readfirstlane(s_ntri), 2 * cnt);
+        for (int t = tid >> 6; t < ntri; t += RB / 64) raster_triangle_wave(T, tris[t], C, R, fm, tid & 63);
       }
       __syncthreads();
       // ---- e. interpolation, normalisation, output
@@ -1095,6 +1159,7 @@ struct ReconLayout {
   int32_t *su, *sv, *sz, *sslot, *tu, *tv, *tz;
   uint64_t *srgb, *trgb;
   int2* cuv;
+  uint64_t* tris;
   uint64_t* facemap;
   int32_t* nnidx;
   int n_wg;
@@ -1136,6 +1201,7 @@ size_t recon_layout(const LsGridInfo& gi, int32_t n_tiles, int64_t n, void* base
   L->srgb = A.take<uint64_t>(E);
   L->trgb = A.take<uint64_t>(E);
   L->cuv = A.take<int2>(E);
+  L->tris = A.take<uint64_t>(2 * E);
   L->facemap = A.take<uint64_t>(RR * nwg);
   L->nnidx = A.take<int32_t>(RR * nwg);
   L->n_wg = nwg;
@@ -1263,6 +1329,7 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   rp.tz = L.tz;
   rp.trgb = L.trgb;
   rp.cuv = L.cuv;
+  rp.tris = L.tris;
   rp.facemap = L.facemap;
   rp.nnidx = L.nnidx;
   rp.queue = L.queue;
