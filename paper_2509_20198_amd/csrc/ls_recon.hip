@@ -855,6 +855,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
   __shared__ int s_hdr[5];  // tile index, flags, bin offset, bin count, tile id
   __shared__ int s_flags;
   __shared__ int s_ntri;
+  __shared__ int s_next;
   __shared__ double s_cz;
   const int tid = threadIdx.x;
   const int R = P.R, C = P.C, H = P.H, W2 = 2 * P.H;
@@ -912,6 +913,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       if (tid == 0) {
         s_flags = 0;
         s_ntri = 0;
+        s_next = 0;
       }
       __syncthreads();
       for (int e = tid; e < cnt; e += RB) {
@@ -1026,43 +1028,62 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
         raster_triangle(T, p, q, r, C, R, fm);
       };
       if (has_dt) {
-        for (int a = tid; a < m; a += RB) {
-          const int b0 = ring_nearest(T, T.uv[a].x, T.uv[a].y, a);
-          int b = b0;
-          bool closed = false;
-          int steps = 0;
-          int prev_b = -1;  // second vertex of the last CCW triangle
-          uint64_t hull_key = FACE_NONE;
-          int hull_b = -1;
-          while (steps++ < STAR_MAX_STEPS) {
-            const int c = third_left(T, a, b);
+        // nearest neighbour of every point: the first edge of its star
+        int32_t* __restrict__ nb0 = P.sslot + off;
+        for (int a = tid; a < m; a += RB) nb0[a] = ring_nearest(T, T.uv[a].x, T.uv[a].y, a);
+        __syncthreads();
+        // Each lane walks one star at a time, one third-vertex search per
+        // iteration, and takes the next point from a shared counter as soon
+        // as its star is done, so the lanes of a wave are not held at star
+        // boundaries.  The walk turns counter-clockwise from the nearest
+        // neighbour b0; if it meets the hull it resumes clockwise from b0.
+        int a = atomicAdd(&s_next, 1);
+        int b0 = 0, b = 0, steps = 0, prev_b = -1, hull_b = -1;
+        bool back = false, first = true;
+        uint64_t hull_key = FACE_NONE;
+        auto start = [&]() {
+          b0 = nb0[a];
+          b = b0;
+          steps = 0;
+          prev_b = -1;  // second vertex of the last counter-clockwise triangle
+          hull_b = -1;
+          back = false;
+          first = true;
+          hull_key = FACE_NONE;
+        };
+        if (a < m) start();
+        while (a < m) {
+          bool done = false;
+          if (steps++ >= STAR_MAX_STEPS) {
+            atomicOr(&s_flags, LS_TILE_DEGENERATE);
+            done = true;
+          } else {
+            // forward: triangle (a, b, c) left of a->b; backward: (b, a, c)
+            const int p = back ? b : a, q = back ? a : b;
+            const int c = third_left(T, p, q);
             if (c < 0) {
-              hull_b = b;
-              if (prev_b >= 0) hull_key = face_key(a, prev_b, b);
-              break;
-            }
-            if (a < b && a < c) emit(a, b, c);
-            prev_b = b;
-            b = c;
-            if (b == b0) {
-              closed = true;
-              break;
-            }
-          }
-          if (!closed && steps <= STAR_MAX_STEPS) {
-            b = b0;
-            bool first = true;
-            while (steps++ < STAR_MAX_STEPS) {
-              const int c = third_left(T, b, a);  // triangle (b, a, c)
-              if (c < 0) break;
-              if (first && hull_key == FACE_NONE) hull_key = face_key(b, a, c);
-              first = false;
-              if (a < b && a < c) emit(b, a, c);
+              if (back) {
+                done = true;
+              } else {
+                hull_b = b;
+                if (prev_b >= 0) hull_key = face_key(a, prev_b, b);
+                back = true;
+                b = b0;
+              }
+            } else {
+              if (back && first && hull_key == FACE_NONE) hull_key = face_key(p, q, c);
+              if (back) first = false;
+              if (a < b && a < c) emit(p, q, c);
+              prev_b = b;
               b = c;
+              if (!back && b == b0) done = true;
             }
           }
-          if (steps > STAR_MAX_STEPS) atomicOr(&s_flags, LS_TILE_DEGENERATE);
-          if (hull_b >= 0 && hull_key != FACE_NONE) raster_hull_edge(T, a, hull_b, hull_key, C, R, fm);
+          if (done) {
+            if (hull_b >= 0 && hull_key != FACE_NONE) raster_hull_edge(T, a, hull_b, hull_key, C, R, fm);
+            a = atomicAdd(&s_next, 1);
+            if (a < m) start();
+          }
         }
       }
       __syncthreads();
