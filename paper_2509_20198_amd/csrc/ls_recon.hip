@@ -740,7 +740,7 @@ __device__ __forceinline__ bool tri_texel_box(const Tile& T, int a, int b, int c
 // Triangles whose texel box exceeds this many texels are rasterised after
 // the star phase by a whole wave (one lane per texel of the box), so a few
 // large triangles do not hold up the lanes of a wave that walk their stars.
-constexpr int WAVE_RASTER_TEXELS = 24;
+constexpr int WAVE_RASTER_TEXELS = 8;
 
 // raster_triangle's result, computed by the 64 lanes of a wave: every texel
 // of the box gets the exact top-left test.
