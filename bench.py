@@ -136,6 +136,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-tiles", type=int, default=64, help="oracle sample size (0 = skip)")
     ap.add_argument("--no-secondary", action="store_true", help="skip splat / backward figures")
+    ap.add_argument("--no-backward", action="store_true", help="skip the backward / training figures")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="start with one plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--splat-points", type=int, default=100_000_000)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -149,6 +152,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     ls.load_library()
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 1 GiB read, 1 GiB written")
 
     # ---------------------------------------------------------------- inputs
     work = synth.batch_tiles(seed=2, device=dev)
@@ -276,10 +287,11 @@ def main():
             out["splat"] = bench_splat(args.splat_points, dev)
         except Exception as e:  # secondary figure only
             out["splat"] = {"error": repr(e)}
-        try:
-            out["backward"] = bench_training(dev)
-        except Exception as e:
-            out["backward"] = {"error": repr(e)}
+        if not args.no_backward:
+            try:
+                out["backward"] = bench_training(dev)
+            except Exception as e:
+                out["backward"] = {"error": repr(e)}
 
     # ---------------------------------------------------------------- CPU baseline (oracle)
     if args.cpu_tiles > 0:
@@ -320,7 +332,10 @@ def bench_splat(n_points: int, dev):
     return {"workload": f"{n_points} points, 64x64 tiles, Morton-ordered", "ms": ms, "ms_min": times[0],
             "ms_mean": sum(times) / len(times),
             "points_per_s": n_points / (ms * 1e-3), "algorithmic_GBps": alg_bytes / (ms * 1e-3) / 1e9,
-            "frac_hbm_peak": alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+            "frac_hbm_peak": alg_bytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "traffic": recorded_traffic("ls_splat.hip", "splat_100M_points_traffic.md")
+            if n_points == 100_000_000 else None,
+            "traffic_unit": "HBM bytes per launch (counters)"}
 
 
 def training_set(dev, dense_per_tile: int = 2_000_000, chunk_tiles: int = 16):
