@@ -277,7 +277,7 @@ def main():
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kernels.items())},
         "autotune_bf16_forward": {"choice": tune["choice"], "refine_ms_default": tune["ms_default"],
                                   "refine_ms_tuned": tune["ms_tuned"],
-                                  "configs": "0 direct (4 pixel tiles/wave), 1 LDS 16x16 tile, 2 direct (2 pixel tiles/wave)"},
+                                  "configs": "0 direct (4 pixel tiles/wave), 1 LDS 16x16 tile, 2 direct (2 pixel tiles/wave), 3 LDS tile, persistent with patch prefetch"},
         "tile_status_nonzero": int((status != 0).sum()),
     }
 

@@ -63,12 +63,13 @@ int ls_zero_f32(float* p, int64_t n, hipStream_t st) {
 int ls_conv_num_configs_impl(int layer, int precision, int pass) {
   if (layer < 0 || layer >= LS_NLAYER || precision < 0 || precision > 1 || pass < 0 || pass > 2) return 0;
   // BF16 forward: 0 = direct operand fetch (4 pixel tiles per wave),
-  //   1 = LDS-staged 16x16 tile, 2 = direct with 2 pixel tiles per wave
+  //   1 = LDS-staged 16x16 tile, 2 = direct with 2 pixel tiles per wave,
+  //   3 = LDS tile in persistent workgroups prefetching the next patch
   // BF16 input gradient: 0 / 1 = direct with 4 / 2 pixel tiles per wave
   // FP32 conv (forward, input gradient): 0..3 = channel block cap 32, 16, 8, 4
   // weight gradient (both precisions): 0..2 = 512, 256, 128 pixel chunks
   if (pass == 2) return 3;
-  if (precision == LS_BF16) return pass == 0 ? 3 : 2;
+  if (precision == LS_BF16) return pass == 0 ? 4 : 2;
   return 4;
 }
 int ls_conv_config_get(int layer, int precision, int pass) {

@@ -78,12 +78,24 @@ __device__ __forceinline__ u16x8 load8(const ConvSrc& s, int b, int yy, int xx, 
 
 int launch_direct(const ConvArgsB& a, int nt, int mt, int64_t npix, hipStream_t st);
 
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup i to XCD i % 8),
+// each XCD with its own L2.  This renumbering hands every XCD a contiguous
+// run of output tiles, so the halo rows two neighbouring tiles share are
+// fetched from HBM once, into the one L2 that serves both.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int per = nb / N_XCD, rem = nb - per * N_XCD;
+  const int x = bid % N_XCD, i = bid / N_XCD;
+  return x * per + min(x, rem) + i;
+}
+
 // NT 16-channel output tiles, MT 16-pixel tiles per wave
 template <int NT, int MT>
 __global__ void __launch_bounds__(64 * WAVES) k_conv_bf16(ConvArgsB A) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t npix = (int64_t)A.B * A.Ho * A.Wo;
-  const int64_t wbase = ((int64_t)blockIdx.x * WAVES + wave) * (16 * MT);
+  const int64_t wbase = ((int64_t)xcd_block() * WAVES + wave) * (16 * MT);
   if (wbase >= npix) return;
   const int r16 = lane & 15, g = lane >> 4;
   const int cin = A.src.a.c + A.src.b.c;
@@ -259,8 +271,9 @@ __global__ void __launch_bounds__(256) k_conv_bf16_lds(ConvTileArgs A) {
   const int cin = A.src.a.c + A.src.b.c;
   const int pitch = patch_pitch(cin);
   const int per_img = A.tiles_x * A.tiles_y;
-  const int b = blockIdx.x / per_img;
-  const int t = blockIdx.x - b * per_img;
+  const int blk = xcd_block();
+  const int b = blk / per_img;
+  const int t = blk - b * per_img;
   const int ty0 = (t / A.tiles_x) * TT, tx0 = (t % A.tiles_x) * TT;
   const int iy0 = A.y0 + ty0 - 1, ix0 = A.x0 + tx0 - 1;
   const int chunks = cin / 8;
@@ -343,20 +356,98 @@ __device__ __forceinline__ void load_part(const SrcPart& p, int b, int yy, int x
   }
 }
 
+// Bias, ReLU and the store of one 16 x 16 output tile computed with the MFMA
+// operands swapped (D = channels x pixels): lane (g, r16) holds output pixel
+// (wave * 4 + mt, r16) of the tile with channels nt * 16 + 4g .. + 3, so
+// every lane stores 4 consecutive channels of one pixel (8 bytes as BF16, 16
+// as FP32) and a wave covers 16 whole pixels per store: no LDS staging.  The
+// 2 x 2 average pool pairs rows mt, mt + 1 inside the lane and columns r16,
+// r16 ^ 1 across lanes, adding in the order of the staged epilogue (top pair,
+// bottom pair, then their sum), so both epilogues give identical bits.
+template <int NT>
+__device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f32x4 (&acc)[4][NT], int b, int ty0,
+                                                  int tx0, int wave, int g, int r16) {
+  const int cout = A.cout;
+  const int ox = tx0 + r16;
+  const int64_t row0 = (int64_t)b * A.Ho;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int c0 = nt * 16 + 4 * g;
+    if (c0 >= cout) continue;  // only the 4-channel head leaves lanes idle
+    float bias[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias[r] = A.bias ? A.bias[c0 + r] : 0.f;
+    float q[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = acc[mt][nt][r] + bias[r];
+        if (A.relu) v = fmaxf(v, 0.f);
+        q[mt][r] = v;
+      }
+    if (A.out_f32) {
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int oy = ty0 + wave * 4 + mt;
+        if (oy < A.Ho && ox < A.Wo)
+          *reinterpret_cast<float4*>(A.out_f32 + ((row0 + oy) * A.Wo + ox) * cout + c0) =
+              make_float4(q[mt][0], q[mt][1], q[mt][2], q[mt][3]);
+      }
+      continue;
+    }
+    unsigned short h[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[mt][r] = f2bf(q[mt][r]);
+      const int oy = ty0 + wave * 4 + mt;
+      if (A.out_bf16 && oy < A.Ho && ox < A.Wo) {
+        uint2 u;
+        u.x = (uint32_t)h[mt][0] | ((uint32_t)h[mt][1] << 16);
+        u.y = (uint32_t)h[mt][2] | ((uint32_t)h[mt][3] << 16);
+        *reinterpret_cast<uint2*>(A.out_bf16 + ((row0 + oy) * A.Wo + ox) * cout + c0) = u;
+      }
+    }
+    if (A.pool_out) {
+      const int Hp = A.Ho / 2, Wp = A.Wo / 2;
+#pragma unroll
+      for (int pr = 0; pr < 2; ++pr) {
+        unsigned short pv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float tl = bf2f(h[2 * pr][r]), bl = bf2f(h[2 * pr + 1][r]);
+          const float tr = __shfl_xor(tl, 1, 64), br = __shfl_xor(bl, 1, 64);
+          pv[r] = f2bf(0.25f * ((tl + tr) + (bl + br)));
+        }
+        if ((r16 & 1) == 0) {
+          const int py = (ty0 + wave * 4 + 2 * pr) / 2, px = ox / 2;
+          uint2 u;
+          u.x = (uint32_t)pv[0] | ((uint32_t)pv[1] << 16);
+          u.y = (uint32_t)pv[2] | ((uint32_t)pv[3] << 16);
+          *reinterpret_cast<uint2*>(A.pool_out + (((int64_t)b * Hp + py) * Wp + px) * cout + c0) = u;
+        }
+      }
+    }
+  }
+}
+
 // k_conv_bf16_lds specialised at compile time on the layer's input: CA
 // channels from part a (nearest-upsampled if UPA, FP32-stored if F32A) and
 // CB from part b.  Patch coordinates are computed once per pixel, the K loop
 // is unrolled with the tap and channel of every step known up to the lane's
 // 8-channel group, and the MFMA sequence per output is the generic kernel's
-// (identical results).
+// with the operands swapped (weights as A, pixels as B), so each lane ends
+// with 4 channels of one pixel and the epilogue needs no LDS.
 template <int NT, int CA, int CB, bool UPA, bool F32A, bool F32B>
 __global__ void __launch_bounds__(256) k_conv_bf16_lds_t(ConvTileArgs A) {
   constexpr int CIN = CA + CB, PITCH = pitch_c(CIN), K = 9 * CIN, KS = (K + 31) / 32, KPAD = KS * 32;
   extern __shared__ __align__(16) unsigned char s_raw[];
   uint16_t* s_in = reinterpret_cast<uint16_t*>(s_raw);
   const int per_img = A.tiles_x * A.tiles_y;
-  const int b = blockIdx.x / per_img;
-  const int t = blockIdx.x - b * per_img;
+  const int blk = xcd_block();
+  const int b = blk / per_img;
+  const int t = blk - b * per_img;
   const int ty0 = (t / A.tiles_x) * TT, tx0 = (t % A.tiles_x) * TT;
   const int iy0 = A.y0 + ty0 - 1, ix0 = A.x0 + tx0 - 1;
   for (int pix = threadIdx.x; pix < PT * PT; pix += 256) {
@@ -396,10 +487,149 @@ __global__ void __launch_bounds__(256) k_conv_bf16_lds_t(ConvTileArgs A) {
       const bf16x8 ab = __builtin_bit_cast(bf16x8, a);
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
-        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ab, bfr[nt], acc[mt][nt], 0, 0, 0);
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], ab, acc[mt][nt], 0, 0, 0);
     }
   }
-  conv_tile_store<NT>(A, acc, b, ty0, tx0, wave, g, r16, s_raw);
+  conv_tile_store_t<NT>(A, acc, b, ty0, tx0, wave, g, r16);
+}
+
+// Packed weight rows in LDS: KPAD elements padded to an odd number of
+// 16-byte units, so the 16 rows a B fragment reads fall in distinct banks.
+constexpr int wpitch_c(int kpad) { return kpad + ((kpad / 8) % 2 == 0 ? 8 : 0); }
+
+// LDS bytes of k_conv_bf16_pipe: the input patch, then the layer's weights.
+constexpr size_t pipe_lds_bytes(int nt, int cin) {
+  return (size_t)PT * PT * pitch_c(cin) * 2 + (size_t)nt * 16 * wpitch_c((9 * cin + 31) / 32 * 32) * 2;
+}
+
+// Persistent form of k_conv_bf16_lds_t: each workgroup copies the layer's
+// packed weights into LDS once, then walks the output tiles tile,
+// tile + gridDim.x, ...; while one tile is multiplied and stored, the next
+// tile's patch is already being loaded into registers (NJ 16-byte units per
+// thread, 32 bytes for units of an FP32 source, converted to BF16 when they
+// are written to LDS), so neither the patch nor the weights are waited for
+// inside the MFMA loop.  Same MFMA sequence and epilogue as
+// k_conv_bf16_lds_t, hence identical results.
+template <int NT, int CA, int CB, bool UPA, bool F32A, bool F32B>
+__global__ void __launch_bounds__(256) k_conv_bf16_pipe(ConvTileArgs A) {
+  constexpr int CIN = CA + CB, C8 = CIN / 8, PITCH = pitch_c(CIN), K = 9 * CIN, KS = (K + 31) / 32, KPAD = KS * 32;
+  constexpr int NU = PT * PT * C8, NJ = (NU + 255) / 256;
+  constexpr int WPITCH = wpitch_c(KPAD), WU = NT * 16 * (KPAD / 8);
+  constexpr bool F32 = F32A || F32B;
+  constexpr int RW = F32 ? 8 : 4;  // 32-bit registers per unit
+  extern __shared__ __align__(16) unsigned char s_raw[];
+  uint16_t* s_in = reinterpret_cast<uint16_t*>(s_raw);
+  uint16_t* s_w = s_in + PT * PT * PITCH;
+  for (int u = threadIdx.x; u < WU; u += 256) {
+    const int row = u / (KPAD / 8), c8 = u - row * (KPAD / 8);
+    *reinterpret_cast<u16x8*>(s_w + row * WPITCH + 8 * c8) =
+        *reinterpret_cast<const u16x8*>(A.wp + (int64_t)row * KPAD + 8 * c8);
+  }
+  const int per_img = A.tiles_x * A.tiles_y, ntiles = A.B * per_img;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  uint32_t pf[NJ][RW];
+  auto fetch = [&](int tile) {
+    const int b = tile / per_img, t = tile - b * per_img;
+    const int iy0 = A.y0 + (t / A.tiles_x) * TT - 1, ix0 = A.x0 + (t % A.tiles_x) * TT - 1;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+      for (int r = 0; r < RW; ++r) pf[j][r] = 0u;
+      const int u = threadIdx.x + 256 * j;
+      if (u < NU) {
+        const int pix = u / C8, ch = u - pix * C8;
+        const int py = pix / PT, px = pix - py * PT;
+        const int yy = iy0 + py, xx = ix0 + px;
+        const bool ina = ch < CA / 8;
+        const SrcPart& p = ina ? A.src.a : A.src.b;
+        const int cc = ina ? ch * 8 : ch * 8 - CA;
+        const bool up = ina && UPA;
+        const int sy = up ? (yy >> 1) : yy - p.oy, sx = up ? (xx >> 1) : xx - p.ox;
+        if (yy >= 0 && xx >= 0 && yy < A.H && xx < A.W && sy >= 0 && sx >= 0 && sy < p.h && sx < p.w) {
+          const int64_t o = (((int64_t)b * p.h + sy) * p.w + sx) * p.stride + p.coff + cc;
+          if ((ina && F32A) || (!ina && F32B)) {
+            const uint4 f0 = *reinterpret_cast<const uint4*>(p.f32 + o);
+            const uint4 f1 = *reinterpret_cast<const uint4*>(p.f32 + o + 4);
+            pf[j][0] = f0.x;
+            pf[j][1] = f0.y;
+            pf[j][2] = f0.z;
+            pf[j][3] = f0.w;
+            pf[j][RW - 4] = f1.x;
+            pf[j][RW - 3] = f1.y;
+            pf[j][RW - 2] = f1.z;
+            pf[j][RW - 1] = f1.w;
+          } else {
+            const uint4 v = *reinterpret_cast<const uint4*>(p.bf16 + o);
+            pf[j][0] = v.x;
+            pf[j][1] = v.y;
+            pf[j][2] = v.z;
+            pf[j][3] = v.w;
+          }
+        }
+      }
+    }
+  };
+  int tile = xcd_block();
+  if (tile >= ntiles) return;
+  fetch(tile);
+  const uint16_t* wrow = s_w + r16 * WPITCH + 8 * g;
+  const uint16_t* base = s_in + (wave * 4 * PT + r16) * PITCH;
+  for (;;) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int u = threadIdx.x + 256 * j;
+      if (u < NU) {
+        const int pix = u / C8, ch = u - pix * C8;
+        const bool ina = ch < CA / 8;
+        u16x8 v;
+        if ((ina && F32A) || (!ina && F32B)) {
+#pragma unroll
+          for (int r = 0; r < 8; ++r) v[r] = f2bf(__builtin_bit_cast(float, pf[j][r]));
+        } else {
+          const uint4 q = make_uint4(pf[j][0], pf[j][1], pf[j][2], pf[j][3]);
+          v = __builtin_bit_cast(u16x8, q);
+        }
+        *reinterpret_cast<u16x8*>(s_in + pix * PITCH + ch * 8) = v;
+      }
+    }
+    __syncthreads();
+    const int b = tile / per_img, t = tile - b * per_img;
+    const int ty0 = (t / A.tiles_x) * TT, tx0 = (t % A.tiles_x) * TT;
+    const int next = tile + (int)gridDim.x;
+    if (next < ntiles) fetch(next);
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = ks * 32 + 8 * g;
+      bf16x8 bfr[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        bfr[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(wrow + nt * 16 * WPITCH + ks * 32));
+      const bool kv = k < K;
+      const int tap = kv ? k / CIN : 0;
+      const int ci = k - tap * CIN;
+      const int ky = tap / 3, kx = tap - 3 * ky;
+      const uint16_t* pb = base + (ky * PT + kx) * PITCH + ci;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (kv) a = *reinterpret_cast<const u16x8*>(pb + mt * PT * PITCH);
+        const bf16x8 ab = __builtin_bit_cast(bf16x8, a);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], ab, acc[mt][nt], 0, 0, 0);
+      }
+    }
+    conv_tile_store_t<NT>(A, acc, b, ty0, tx0, wave, g, r16);
+    if (next >= ntiles) break;
+    tile = next;
+    __syncthreads();  // every wave is done reading the patch before it is overwritten
+  }
 }
 
 __global__ void k_avgpool_bf16(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int B, int H, int W, int C) {
@@ -623,7 +853,8 @@ int conv_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* packed, con
 }
 
 int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed, const float* w, uint16_t* out_bf16,
-                  float* out_f32, uint16_t* pool_out, int relu, int y0, int x0, int Ho, int Wo, hipStream_t st) {
+                  float* out_f32, uint16_t* pool_out, int relu, int y0, int x0, int Ho, int Wo, bool pipe,
+                  hipStream_t st) {
   ConvTileArgs a;
   a.src = s;
   a.B = B;
@@ -656,13 +887,44 @@ int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed,
     return s.a.c == ca && s.b.c == cb && (s.a.up != 0) == upa && (s.a.f32 != nullptr) == f32a &&
            (cb == 0 || ((s.b.f32 != nullptr) == f32b && !s.b.up));
   };
+  // persistent pipelined form: as many workgroups as fit on the device at once
+#define LS_PIPE(L, N, CA, CB, UPA, F32A, F32B)                                                           \
+  if (pipe && l == L && nt == N && is(CA, CB, UPA, F32A, F32B)) {                                        \
+    auto* fn = &k_conv_bf16_pipe<N, CA, CB, UPA, F32A, F32B>;                                            \
+    constexpr size_t plds = pipe_lds_bytes(N, CA + CB);                                                  \
+    static_assert(plds <= LDS_MAX, "pipelined tile exceeds LDS");                                       \
+    if (plds > 65536)                                                                                    \
+      LS_HOST_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),                               \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds));         \
+    int per_cu = 0, dev = 0, cus = 0;                                                                    \
+    LS_HOST_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, plds));                \
+    LS_HOST_CHECK(hipGetDevice(&dev));                                                                   \
+    LS_HOST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));             \
+    const int64_t want = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);                                \
+    const dim3 pgrid((unsigned)std::min<int64_t>(want, (int64_t)grid.x));                               \
+    hipLaunchKernelGGL((k_conv_bf16_pipe<N, CA, CB, UPA, F32A, F32B>), pgrid, dim3(256), plds, st, a);  \
+    LS_LAUNCH_CHECK();                                                                                   \
+    return LS_OK;                                                                                        \
+  }
+  LS_PIPE(0, 1, 8, 0, false, true, false)
+  LS_PIPE(1, 1, 16, 0, false, false, false)
+  LS_PIPE(2, 2, 16, 0, false, false, false)
+  LS_PIPE(3, 2, 32, 0, false, false, false)
+  LS_PIPE(4, 4, 32, 0, false, false, false)
+  LS_PIPE(5, 4, 64, 0, false, false, false)
+  LS_PIPE(6, 2, 64, 32, true, false, false)
+  LS_PIPE(7, 2, 32, 0, false, false, false)
+  LS_PIPE(8, 1, 32, 16, true, false, false)
+  LS_PIPE(9, 1, 16, 0, false, false, false)
+  LS_PIPE(10, 1, 16, 8, false, false, true)
+#undef LS_PIPE
 #define LS_SPEC(L, N, CA, CB, UPA, F32A, F32B)                                                          \
   if (l == L && nt == N && is(CA, CB, UPA, F32A, F32B)) {                                            \
-    if (lds > 65536)                                                                                 \
+    if (patch > 65536)                                                                               \
       LS_HOST_CHECK(hipFuncSetAttribute(                                                             \
           reinterpret_cast<const void*>(&k_conv_bf16_lds_t<N, CA, CB, UPA, F32A, F32B>),             \
-          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                                    \
-    hipLaunchKernelGGL((k_conv_bf16_lds_t<N, CA, CB, UPA, F32A, F32B>), grid, dim3(256), lds, st, a); \
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)patch));                                  \
+    hipLaunchKernelGGL((k_conv_bf16_lds_t<N, CA, CB, UPA, F32A, F32B>), grid, dim3(256), patch, st, a); \
     LS_LAUNCH_CHECK();                                                                               \
     return LS_OK;                                                                                    \
   }
@@ -754,18 +1016,20 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   SrcPart X = src_plain(x, 8, R, R, 8, 0, nullptr);
   const SrcPart none = src_none();
   // per layer: tiling variant 0 = direct (operands from global memory, 4 pixel
-  // tiles per wave), 1 = LDS-staged 16 x 16 tile (default), 2 = direct with 2
-  // pixel tiles per wave
+  // tiles per wave), 1 = LDS-staged 16 x 16 tile, 2 = direct with 2
+  // pixel tiles per wave, 3 = the LDS tile in persistent workgroups that
+  // prefetch the next patch
   auto variant = [&](int l) {
     const int c = ls_conv_config_get(l, LS_BF16, 0);
-    return c < 0 ? 1 : c;
+    return c >= 0 ? c : (l == LS_NLAYER - 1 ? 1 : 3);  // default: persistent tile, plain tile for the head
   };
   // a layer feeding an average pool writes the pooled tensor too when it uses the LDS tile
   auto conv = [&](const ConvSrc& s, int H, int l, uint16_t* out, uint16_t* pooled) -> int {
     const int cin_l = LS_LAYERS[l].cin;
-    if (variant(l) == 1 && (size_t)PT * PT * patch_pitch(cin_l) * 2 <= LDS_MAX) {
+    if ((variant(l) == 1 || variant(l) == 3) && (size_t)PT * PT * patch_pitch(cin_l) * 2 <= LDS_MAX) {
       const bool fuse = pooled && H % TT == 0;
-      LS_TRYB(conv_bf16_lds(s, B, H, l, packed, w, out, nullptr, fuse ? pooled : nullptr, 1, 0, 0, H, H, st));
+      LS_TRYB(conv_bf16_lds(s, B, H, l, packed, w, out, nullptr, fuse ? pooled : nullptr, 1, 0, 0, H, H,
+                            variant(l) == 3, st));
       if (pooled && !fuse) return pool_bf16(out, pooled, B, H, LS_LAYERS[l].cout, st);
       return LS_OK;
     }
@@ -787,9 +1051,9 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   LS_TRYB(conv(cs(bpart(A7, 32, R2), none), R2, 7, A8, nullptr));
   LS_TRYB(conv(cs(u8, bpart(A2, 16, R)), R, 8, A9, nullptr));
   LS_TRYB(conv(cs(bpart(A9, 16, R), none), R, 9, A10, nullptr));
-  if (variant(10) == 1 && (size_t)PT * PT * patch_pitch(24) * 2 <= LDS_MAX)
+  if ((variant(10) == 1 || variant(10) == 3) && (size_t)PT * PT * patch_pitch(24) * 2 <= LDS_MAX)
     return conv_bf16_lds(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,
-                         gi.res, gi.res, st);
+                         gi.res, gi.res, variant(10) == 3, st);
   return conv_bf16(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, 0, gi.pad, gi.pad, gi.res, gi.res,
                    variant(10) == 2 ? 2 : 4, st);
 }
