@@ -192,7 +192,9 @@ __device__ __forceinline__ uint32_t splat_colour(const SplatRegs& r, int s, int 
 // first max-reduced in an LDS window indexed by Morton code and flushed with
 // one global 64-bit atomic max per touched texel; otherwise every point
 // goes straight to a global atomic max.
-__global__ void __launch_bounds__(SPLAT_THREADS) k_splat(SplatParams p) {
+// At most 72 VGPRs (seven waves per SIMD): the loads of more workgroups are
+// in flight at once, which pays more than the few registers it costs.
+__global__ void __launch_bounds__(SPLAT_THREADS, 7) k_splat(SplatParams p) {
   __shared__ unsigned long long s_win[SPLAT_WIN];
   __shared__ uint32_t s_lo[SPLAT_THREADS / 64], s_hi[SPLAT_THREADS / 64];
   __shared__ unsigned long long s_drop[SPLAT_THREADS / 64];
