@@ -449,6 +449,52 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
   return best;
 }
 
+// Nearest points of an 8 x 8 block of texels, one texel per lane of a wave
+// (lane = 8 * row + column): every lane scans the same candidate list, the
+// points of the buckets under the block widened by one bucket on each side,
+// so the loops are uniform and each point is read once per wave (an LDS
+// broadcast).  A texel keeps the scan's answer when its best squared
+// distance is below the squared distance to every side of the scanned
+// bucket rectangle that faces more buckets (sides rounded inwards by one raw
+// unit); otherwise it falls back to ring_nearest.  Same order on
+// (d^2, v, u), so the result equals ring_nearest's.
+__device__ int nearest_block(const Tile& T, int q0, int C, int R, int bi, int bj, int lane, int& qx, int& qy) {
+  const int G = T.G;
+  const int i = bi * 8 + (lane >> 3), j = bj * 8 + (lane & 7);
+  qx = q0 + j * C;
+  qy = q0 + i * C;
+  const int i1 = min(bi * 8 + 7, R - 1), j1 = min(bj * 8 + 7, R - 1);
+  const int bx0 = max(bucket_1d(q0 + bj * 8 * C + T.H, G, T.W2) - 1, 0);
+  const int bx1 = min(bucket_1d(q0 + j1 * C + T.H, G, T.W2) + 1, G - 1);
+  const int by0 = max(bucket_1d(q0 + bi * 8 * C + T.H, G, T.W2) - 1, 0);
+  const int by1 = min(bucket_1d(q0 + i1 * C + T.H, G, T.W2) + 1, G - 1);
+  int best = -1, bu = 0, bv = 0;
+  double bd = 0.0;  // squared distance, exact in double (below 2^36)
+  for (int by = by0; by <= by1; ++by) {
+    const int e = T.boff[by * G + bx1 + 1];
+    for (int p = T.boff[by * G + bx0]; p < e; ++p) {  // buckets bx0..bx1 of a row are contiguous
+      const int2 q = T.uv[p];
+      const double dx = q.x - qx, dy = q.y - qy;
+      const double d = fma(dx, dx, dy * dy);
+      if (best < 0 || d < bd || (d == bd && (q.y < bv || (q.y == bv && q.x < bu)))) {
+        best = p;
+        bd = d;
+        bu = q.x;
+        bv = q.y;
+      }
+    }
+  }
+  // distance from q to the unscanned buckets (grid-local coordinates)
+  const double fx = qx + T.H, fy = qy + T.H;
+  double L = 1e300;
+  if (bx0 > 0) L = fmin(L, fx - (ceil(bx0 * T.bw) + 1.0));
+  if (bx1 < G - 1) L = fmin(L, (floor((bx1 + 1) * T.bw) - 1.0) - fx);
+  if (by0 > 0) L = fmin(L, fy - (ceil(by0 * T.bw) + 1.0));
+  if (by1 < G - 1) L = fmin(L, (floor((by1 + 1) * T.bw) - 1.0) - fy);
+  if (best >= 0 && (L >= 1e300 || (L > 0.0 && bd < L * L))) return best;
+  return ring_nearest(T, qx, qy, -1);
+}
+
 // Bucket index range of the tile-local box [x0, x1] x [y0, y1] widened by
 // `slack` raw units, clamped to the grid.
 struct BucketBox {
@@ -993,10 +1039,18 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       const uint64_t* Tc = P.srgb + off;
       // ---- c. nearest point per texel; face map reset
       const int q0 = -H + C / 2;
-      for (int tt = tid; tt < RR; tt += RB) {
-        const int i = tt / R, j = tt - i * R;
-        nn[tt] = ring_nearest(T, q0 + j * C, q0 + i * C, -1);
-        fm[tt] = FACE_NONE;
+      {
+        const int nbs = (R + 7) / 8, lane = tid & 63;
+        for (int blk = tid >> 6; blk < nbs * nbs; blk += RB / 64) {
+          const int bi = blk / nbs, bj = blk - bi * nbs;
+          int qx, qy;
+          const int b = nearest_block(T, q0, C, R, bi, bj, lane, qx, qy);
+          const int i = bi * 8 + (lane >> 3), j = bj * 8 + (lane & 7);
+          if (i < R && j < R) {
+            nn[i * R + j] = b;
+            fm[i * R + j] = FACE_NONE;
+          }
+        }
       }
       // collinearity check
       bool noncol = false;
