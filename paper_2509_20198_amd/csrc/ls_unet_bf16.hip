@@ -364,36 +364,46 @@ __device__ __forceinline__ void load_part(const SrcPart& p, int b, int yy, int x
 // 2 x 2 average pool pairs rows mt, mt + 1 inside the lane and columns r16,
 // r16 ^ 1 across lanes, adding in the order of the staged epilogue (top pair,
 // bottom pair, then their sum), so both epilogues give identical bits.
+// The bias of the 4 channels lane (g, r16) stores for each channel tile.
 template <int NT>
-__device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f32x4 (&acc)[4][NT], int b, int ty0,
-                                                  int tx0, int wave, int g, int r16) {
+__device__ __forceinline__ void load_bias_t(const ConvTileArgs& A, int g, float (&bias)[NT][4]) {
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = nt * 16 + 4 * g + r;
+      bias[nt][r] = (A.bias && c < A.cout) ? A.bias[c] : 0.f;
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f32x4 (&acc)[4][NT],
+                                                  const float (&bias)[NT][4], int b, int ty0, int tx0, int wave,
+                                                  int g, int r16) {
   const int cout = A.cout;
-  const int ox = tx0 + r16;
-  const int64_t row0 = (int64_t)b * A.Ho;
+  const int ox = tx0 + r16, oy0 = ty0 + wave * 4;
+  // a whole tile inside the output needs no per-row test
+  const bool full = ty0 + TT <= A.Ho && tx0 + TT <= A.Wo;
+  const int64_t pix0 = ((int64_t)b * A.Ho + oy0) * A.Wo + ox;  // output pixel of row mt = 0
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int c0 = nt * 16 + 4 * g;
     if (c0 >= cout) continue;  // only the 4-channel head leaves lanes idle
-    float bias[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bias[r] = A.bias ? A.bias[c0 + r] : 0.f;
     float q[4][4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float v = acc[mt][nt][r] + bias[r];
+        float v = acc[mt][nt][r] + bias[nt][r];
         if (A.relu) v = fmaxf(v, 0.f);
         q[mt][r] = v;
       }
+    const int64_t off0 = pix0 * cout + c0, row = (int64_t)A.Wo * cout;
     if (A.out_f32) {
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) {
-        const int oy = ty0 + wave * 4 + mt;
-        if (oy < A.Ho && ox < A.Wo)
-          *reinterpret_cast<float4*>(A.out_f32 + ((row0 + oy) * A.Wo + ox) * cout + c0) =
-              make_float4(q[mt][0], q[mt][1], q[mt][2], q[mt][3]);
-      }
+      for (int mt = 0; mt < 4; ++mt)
+        if (full || (oy0 + mt < A.Ho && ox < A.Wo))
+          *reinterpret_cast<float4*>(A.out_f32 + off0 + mt * row) = make_float4(q[mt][0], q[mt][1], q[mt][2], q[mt][3]);
       continue;
     }
     unsigned short h[4][4];
@@ -401,12 +411,11 @@ __device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f
     for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) h[mt][r] = f2bf(q[mt][r]);
-      const int oy = ty0 + wave * 4 + mt;
-      if (A.out_bf16 && oy < A.Ho && ox < A.Wo) {
+      if (A.out_bf16 && (full || (oy0 + mt < A.Ho && ox < A.Wo))) {
         uint2 u;
         u.x = (uint32_t)h[mt][0] | ((uint32_t)h[mt][1] << 16);
         u.y = (uint32_t)h[mt][2] | ((uint32_t)h[mt][3] << 16);
-        *reinterpret_cast<uint2*>(A.out_bf16 + ((row0 + oy) * A.Wo + ox) * cout + c0) = u;
+        *reinterpret_cast<uint2*>(A.out_bf16 + off0 + mt * row) = u;
       }
     }
     if (A.pool_out) {
@@ -490,7 +499,9 @@ __global__ void __launch_bounds__(256) k_conv_bf16_lds_t(ConvTileArgs A) {
         acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], ab, acc[mt][nt], 0, 0, 0);
     }
   }
-  conv_tile_store_t<NT>(A, acc, b, ty0, tx0, wave, g, r16);
+  float bias[NT][4];
+  load_bias_t<NT>(A, g, bias);
+  conv_tile_store_t<NT>(A, acc, bias, b, ty0, tx0, wave, g, r16);
 }
 
 // Packed weight rows in LDS: KPAD elements padded to an odd number of
@@ -573,6 +584,8 @@ __global__ void __launch_bounds__(256) k_conv_bf16_pipe(ConvTileArgs A) {
   int tile = xcd_block();
   if (tile >= ntiles) return;
   fetch(tile);
+  float bias[NT][4];
+  load_bias_t<NT>(A, g, bias);
   const uint16_t* wrow = s_w + r16 * WPITCH + 8 * g;
   const uint16_t* base = s_in + (wave * 4 * PT + r16) * PITCH;
   for (;;) {
@@ -625,7 +638,7 @@ __global__ void __launch_bounds__(256) k_conv_bf16_pipe(ConvTileArgs A) {
           acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], ab, acc[mt][nt], 0, 0, 0);
       }
     }
-    conv_tile_store_t<NT>(A, acc, b, ty0, tx0, wave, g, r16);
+    conv_tile_store_t<NT>(A, acc, bias, b, ty0, tx0, wave, g, r16);
     if (next >= ntiles) break;
     tile = next;
     __syncthreads();  // every wave is done reading the patch before it is overwritten
