@@ -254,6 +254,13 @@ def main():
                 "avg_launch_ms": ms_dom / kernels[dom]["launches_per_step"],
                 "algorithmic_per_step": f"{bytes_step / 1e6:.1f} MB written (x_out)"}
     log(f"dominant kernel group: {dom} ({kernels[dom]['ms_per_step']:.3f} ms/step)")
+    # the convolutions against the matrix-core peak, whatever group dominates
+    conv_ms = kernels.get("conv_bf16", {}).get("ms_per_step", 0.0)
+    conv_tf = flops_tile * nt / (conv_ms * 1e-3) / 1e12 if conv_ms > 0 else None
+    roof_conv = {"kernel": "conv_bf16 (all 11 conv launches of a step)", "bound": "mfma", "achieved": conv_tf,
+                 "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                 "frac": conv_tf / PEAK_BF16_TFLOPS if conv_tf else None, "ms_per_step": conv_ms,
+                 "algorithmic_per_step": f"{flops_tile * nt / 1e9:.1f} GFLOP ({flops_tile / 1e9:.4f} GFLOP/tile)"}
 
     out = {
         "metric": METRIC,
@@ -272,6 +279,7 @@ def main():
                                "(log-uniform), fBm terrain; recon + BF16 refine in one HIP graph",
                    "tiles": nt, "sparse_points": ps.n, "res": res, "pad": g.pad, "grid": f"{R}x{R}x8"},
         "roofline": roof,
+        "roofline_conv": roof_conv,
         "fp32_plain": {"tiles_per_s": nt / (ms32 * 1e-3), "ms_per_step": ms32},
         "bf16_vs_fp32": ms32 / ms16,
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kernels.items())},
@@ -317,7 +325,7 @@ def bench_splat(n_points: int, dev):
     nd = torch.zeros(1, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     fn = lambda: ls.splat_points(g, x, y, z, rgb, ts, nslots, keys=keys, n_dropped=nd)  # noqa: E731
-    for _ in range(3):
+    for _ in range(10):
         fn()
     torch.cuda.synchronize()
     ls.trace_enable(True)
