@@ -513,6 +513,8 @@ constexpr size_t pipe_lds_bytes(int nt, int cin) {
   return (size_t)PT * PT * pitch_c(cin) * 2 + (size_t)nt * 16 * wpitch_c((9 * cin + 31) / 32 * 32) * 2;
 }
 
+// MINW is the layer's register budget as waves per SIMD (measured per layer:
+// the narrow layers gain from more waves, the widest spill below one).
 // Persistent form of k_conv_bf16_lds_t: each workgroup copies the layer's
 // packed weights into LDS once, then walks the output tiles tile,
 // tile + gridDim.x, ...; while one tile is multiplied and stored, the next
@@ -521,8 +523,8 @@ constexpr size_t pipe_lds_bytes(int nt, int cin) {
 // are written to LDS), so neither the patch nor the weights are waited for
 // inside the MFMA loop.  Same MFMA sequence and epilogue as
 // k_conv_bf16_lds_t, hence identical results.
-template <int NT, int CA, int CB, bool UPA, bool F32A, bool F32B>
-__global__ void __launch_bounds__(256) k_conv_bf16_pipe(ConvTileArgs A) {
+template <int NT, int CA, int CB, bool UPA, bool F32A, bool F32B, int MINW>
+__global__ void __launch_bounds__(256, MINW) k_conv_bf16_pipe(ConvTileArgs A) {
   constexpr int CIN = CA + CB, C8 = CIN / 8, PITCH = pitch_c(CIN), K = 9 * CIN, KS = (K + 31) / 32, KPAD = KS * 32;
   constexpr int NU = PT * PT * C8, NJ = (NU + 255) / 256;
   constexpr int WPITCH = wpitch_c(KPAD), WU = NT * 16 * (KPAD / 8);
@@ -901,9 +903,9 @@ int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed,
            (cb == 0 || ((s.b.f32 != nullptr) == f32b && !s.b.up));
   };
   // persistent pipelined form: as many workgroups as fit on the device at once
-#define LS_PIPE(L, N, CA, CB, UPA, F32A, F32B)                                                           \
+#define LS_PIPE(L, N, CA, CB, UPA, F32A, F32B, W)                                                        \
   if (pipe && l == L && nt == N && is(CA, CB, UPA, F32A, F32B)) {                                        \
-    auto* fn = &k_conv_bf16_pipe<N, CA, CB, UPA, F32A, F32B>;                                            \
+    auto* fn = &k_conv_bf16_pipe<N, CA, CB, UPA, F32A, F32B, W>;                                         \
     constexpr size_t plds = pipe_lds_bytes(N, CA + CB);                                                  \
     static_assert(plds <= LDS_MAX, "pipelined tile exceeds LDS");                                       \
     if (plds > 65536)                                                                                    \
@@ -915,21 +917,21 @@ int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed,
     LS_HOST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));             \
     const int64_t want = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);                                \
     const dim3 pgrid((unsigned)std::min<int64_t>(want, (int64_t)grid.x));                               \
-    hipLaunchKernelGGL((k_conv_bf16_pipe<N, CA, CB, UPA, F32A, F32B>), pgrid, dim3(256), plds, st, a);  \
+    hipLaunchKernelGGL((k_conv_bf16_pipe<N, CA, CB, UPA, F32A, F32B, W>), pgrid, dim3(256), plds, st, a); \
     LS_LAUNCH_CHECK();                                                                                   \
     return LS_OK;                                                                                        \
   }
-  LS_PIPE(0, 1, 8, 0, false, true, false)
-  LS_PIPE(1, 1, 16, 0, false, false, false)
-  LS_PIPE(2, 2, 16, 0, false, false, false)
-  LS_PIPE(3, 2, 32, 0, false, false, false)
-  LS_PIPE(4, 4, 32, 0, false, false, false)
-  LS_PIPE(5, 4, 64, 0, false, false, false)
-  LS_PIPE(6, 2, 64, 32, true, false, false)
-  LS_PIPE(7, 2, 32, 0, false, false, false)
-  LS_PIPE(8, 1, 32, 16, true, false, false)
-  LS_PIPE(9, 1, 16, 0, false, false, false)
-  LS_PIPE(10, 1, 16, 8, false, false, true)
+  LS_PIPE(0, 1, 8, 0, false, true, false, 1)
+  LS_PIPE(1, 1, 16, 0, false, false, false, 2)
+  LS_PIPE(2, 2, 16, 0, false, false, false, 2)
+  LS_PIPE(3, 2, 32, 0, false, false, false, 2)
+  LS_PIPE(4, 4, 32, 0, false, false, false, 2)
+  LS_PIPE(5, 4, 64, 0, false, false, false, 1)
+  LS_PIPE(6, 2, 64, 32, true, false, false, 1)
+  LS_PIPE(7, 2, 32, 0, false, false, false, 2)
+  LS_PIPE(8, 1, 32, 16, true, false, false, 3)
+  LS_PIPE(9, 1, 16, 0, false, false, false, 2)
+  LS_PIPE(10, 1, 16, 8, false, false, true, 2)
 #undef LS_PIPE
 #define LS_SPEC(L, N, CA, CB, UPA, F32A, F32B)                                                          \
   if (l == L && nt == N && is(CA, CB, UPA, F32A, F32B)) {                                            \
@@ -1034,7 +1036,7 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   // prefetch the next patch
   auto variant = [&](int l) {
     const int c = ls_conv_config_get(l, LS_BF16, 0);
-    return c >= 0 ? c : (l == LS_NLAYER - 1 ? 1 : 3);  // default: persistent tile, plain tile for the head
+    return c >= 0 ? c : 3;  // default: the persistent tile
   };
   // a layer feeding an average pool writes the pooled tensor too when it uses the LDS tile
   auto conv = [&](const ConvSrc& s, int H, int l, uint16_t* out, uint16_t* pooled) -> int {
