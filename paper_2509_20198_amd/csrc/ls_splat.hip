@@ -192,9 +192,9 @@ __device__ __forceinline__ uint32_t splat_colour(const SplatRegs& r, int s, int 
 // first max-reduced in an LDS window indexed by Morton code and flushed with
 // one global 64-bit atomic max per touched texel; otherwise every point
 // goes straight to a global atomic max.
-// At most 72 VGPRs (seven waves per SIMD): the loads of more workgroups are
-// in flight at once, which pays more than the few registers it costs.
-__global__ void __launch_bounds__(SPLAT_THREADS, 7) k_splat(SplatParams p) {
+// At most 64 VGPRs (eight waves per SIMD): the loads of more workgroups are
+// in flight at once, which pays more than the one register spilled.
+__global__ void __launch_bounds__(SPLAT_THREADS, 8) k_splat(SplatParams p) {
   __shared__ unsigned long long s_win[SPLAT_WIN];
   __shared__ uint32_t s_lo[SPLAT_THREADS / 64], s_hi[SPLAT_THREADS / 64];
   __shared__ unsigned long long s_drop[SPLAT_THREADS / 64];
@@ -207,12 +207,12 @@ __global__ void __launch_bounds__(SPLAT_THREADS, 7) k_splat(SplatParams p) {
     SplatRegs r;
     splat_load(p, base, tid, r);
     unsigned long long key[SPLAT_PPT];
-    int gxs[SPLAT_PPT], gys[SPLAT_PPT];
+    uint32_t mcs[SPLAT_PPT];  // Morton code of each point's texel
     uint32_t lo = 0xFFFFFFFFu, hi = 0;
 #pragma unroll
     for (int s = 0; s < SPLAT_PPT; ++s) {
       key[s] = 0;
-      gxs[s] = gys[s] = 0;
+      mcs[s] = 0;
       if (!((r.valid >> s) & 1u)) continue;
       int gx, gy;
       unsigned long long kk;
@@ -221,16 +221,17 @@ __global__ void __launch_bounds__(SPLAT_THREADS, 7) k_splat(SplatParams p) {
         ++dropped;
         continue;
       }
-      key[s] = kk;
-      gxs[s] = gx;
-      gys[s] = gy;
-      if (p.morton_ok) {
-        const uint32_t mc = spread16((uint32_t)gx) | (spread16((uint32_t)gy) << 1);
-        lo = min(lo, mc);
-        hi = max(hi, mc);
+      if (!p.morton_ok) {
+        // texel grid too wide for 16-bit Morton halves: straight to the key array
+        atomicMax(&p.keys[cell_of(p, gx, gy)], kk);
+        continue;
       }
+      key[s] = kk;
+      const uint32_t mc = spread16((uint32_t)gx) | (spread16((uint32_t)gy) << 1);
+      mcs[s] = mc;
+      lo = min(lo, mc);
+      hi = max(hi, mc);
     }
-    bool use_lds = false;
     if (p.morton_ok) {
       // block min / max of the Morton codes: wave shuffles, then one value per wave
       for (int o = 32; o > 0; o >>= 1) {
@@ -252,14 +253,10 @@ __global__ void __launch_bounds__(SPLAT_THREADS, 7) k_splat(SplatParams p) {
       // provably uniform control flow
       blo = (uint32_t)__builtin_amdgcn_readfirstlane((int)blo);
       bhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)bhi);
-      use_lds = bhi >= blo && (bhi - blo) < (uint32_t)SPLAT_WIN;
-      if (use_lds) {
+      if (bhi >= blo && (bhi - blo) < (uint32_t)SPLAT_WIN) {
 #pragma unroll
         for (int s = 0; s < SPLAT_PPT; ++s)
-          if (key[s]) {
-            const uint32_t mc = spread16((uint32_t)gxs[s]) | (spread16((uint32_t)gys[s]) << 1);
-            atomicMax(&s_win[mc - blo], key[s]);
-          }
+          if (key[s]) atomicMax(&s_win[mcs[s] - blo], key[s]);
         __syncthreads();
         const int span = (int)(bhi - blo) + 1;
         for (int w = tid; w < span; w += SPLAT_THREADS) {
@@ -271,12 +268,12 @@ __global__ void __launch_bounds__(SPLAT_THREADS, 7) k_splat(SplatParams p) {
         }
         // the next batch's first barrier (or the kernel's end) orders these
         // clears before the window is used again
-      }
-    }
-    if (!use_lds) {
+      } else {
 #pragma unroll
-      for (int s = 0; s < SPLAT_PPT; ++s)
-        if (key[s]) atomicMax(&p.keys[cell_of(p, gxs[s], gys[s])], key[s]);
+        for (int s = 0; s < SPLAT_PPT; ++s)
+          if (key[s])
+            atomicMax(&p.keys[cell_of(p, (int)compact16(mcs[s]), (int)compact16(mcs[s] >> 1))], key[s]);
+      }
     }
   }
   // one global atomic per workgroup for the dropped count
