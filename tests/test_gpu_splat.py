@@ -62,6 +62,24 @@ def test_splat_morton_chunks_accumulate_and_resolve():
     assert np.array_equal(tex0.cpu().numpy().view(np.uint32), tex_want.view(np.uint32))
 
 
+def test_splat_wide_grid_direct_atomics():
+    """A texel grid wider than 65,536 columns (1,025 tiles of 64 texels):
+    Morton codes no longer fit 16-bit halves and every key goes straight to
+    the global array."""
+    region = synth.Region(origin_x=-70000, origin_y=5000, tiles_x=1025, tiles_y=1, res=64)
+    x, y, z, rgb = _rand(11, region, 60000)
+    ts = np.full(1025, -1, np.int32)
+    ts[[0, 1, 512, 1023, 1024]] = [4, 0, 2, 1, 3]
+    want, wd = oracle.splat(region, x, y, z, rgb, ts, 5)
+    g = ls.Grid.of(region)
+    xt, yt, zt, rt = arrays_to_dev(x, y, z, rgb)
+    keys, nd = ls.splat_points(g, xt, yt, zt, rt, torch.from_numpy(ts).cuda(), 5)
+    torch.cuda.synchronize()
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), want)
+    assert int(nd.item()) == wd
+    assert np.count_nonzero(want) > 0
+
+
 def test_splat_permutation_invariant():
     region = synth.Region(tiles_x=2, tiles_y=2)
     ps = synth.fullres_uniform(region, 100_000, seed=4)
