@@ -143,8 +143,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the per-tile path needs no collective and this build runs on a "
-              "single MI355X; run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only (tiles are independent; how the path would shard over GPUs is "
+              "described in the design notes); run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)

@@ -295,7 +295,7 @@ __global__ void k_resolve(const unsigned long long* __restrict__ keys, int64_t n
     if (!k) continue;
     const int32_t zr = (int32_t)((uint32_t)(k >> 32) ^ 0x80000000u);
     // separate multiply and add, each correctly rounded (no contraction);
-    // float division is IEEE-correct in this build
+    // float division is IEEE-correct with the library's compile flags
     const double hm = (double)zr * scale_z;
     const double h = hm + offset_z;
     tex[i] = make_float4((float)h, (float)((k >> 24) & 0xFF) / 255.0f, (float)((k >> 16) & 0xFF) / 255.0f,
