@@ -391,7 +391,12 @@ def bench_training(dev, train_steps: int = 60):
     gy = torch.randn((nt, g.res, g.res, 4), device=dev, generator=torch.Generator(device=dev).manual_seed(0))
     out = {"workload": f"{nt} tiles (16 x 16), 200-800 sparse points per tile; targets from 2,000,000 dense "
                        f"points per tile", "target_texels_without_points": empty}
+    from paper_2509_20198_amd import autotune as AT
+
     for name, prec in (("fp32", ls.FP32), ("bf16", ls.BF16)):
+        # conv tilings of forward, input gradient and weight gradient for this shape
+        tune = AT.autotune(g, nt, prec, passes=(0, 1, 2), reps=3, force=True)
+        log(f"autotuned {name} forward + backward tilings: {tune['ms_default']:.3f} -> {tune['ms_tuned']:.3f} ms")
         wb = ls.pack_weights_bf16(w0) if prec == ls.BF16 else None
         act = torch.empty(ls.act_bytes(g, nt, prec), dtype=torch.uint8, device=dev)
         ws = ls.alloc_workspace(ls.workspace_bytes(ls.OP_BACKWARD, g, nt, 0, prec), dev)
@@ -408,7 +413,9 @@ def bench_training(dev, train_steps: int = 60):
         ms = Timer().run(step, 5, 2)
         ms_rc = Timer().run(step_recompute, 5, 2)
         out[name] = {"fwd_bwd_ms": ms, "tiles_per_s": nt / (ms * 1e-3), "fwd_bwd_recompute_ms": ms_rc,
-                     "saved_activation_bytes": int(act.numel())}
+                     "saved_activation_bytes": int(act.numel()),
+                     "autotune": {"ms_default": tune["ms_default"], "ms_tuned": tune["ms_tuned"],
+                                  "choice": tune["choice"]}}
         del act, ws
     # training: BF16 convolutions, FP32 weights and optimiser state
     base = float(T.l1_loss(T.linear_baseline(x, g.pad, g.res), t).item())

@@ -293,12 +293,28 @@ __global__ void __launch_bounds__(CT) k_wgrad_tiled(WgradArgs A) {
   }
 }
 
-__global__ void k_reduce_partials(const float* __restrict__ partial, int nchunk, int64_t n, float* __restrict__ out) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// out[i] = sum over chunks of partial[c][i], in a fixed order: RED_SEG
+// consecutive runs of chunks are summed in parallel (each run in chunk
+// order), then the run sums in run order.  A workgroup covers RED_OUT
+// outputs, so enough workgroups run even for a few thousand outputs.
+constexpr int RED_OUT = 16, RED_SEG = CT / RED_OUT;
+__global__ void __launch_bounds__(CT) k_reduce_partials(const float* __restrict__ partial, int nchunk, int64_t n,
+                                                      float* __restrict__ out) {
+  __shared__ float s_run[RED_SEG][RED_OUT];
+  const int o = threadIdx.x % RED_OUT, seg = threadIdx.x / RED_OUT;
+  const int64_t i = blockIdx.x * (int64_t)RED_OUT + o;
+  const int len = (nchunk + RED_SEG - 1) / RED_SEG;
+  const int c0 = seg * len, c1 = min(nchunk, c0 + len);
   float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) s += partial[(int64_t)c * n + i];
-  out[i] = s;
+  if (i < n)
+    for (int c = c0; c < c1; ++c) s += partial[(int64_t)c * n + i];
+  s_run[seg][o] = s;
+  __syncthreads();
+  if (seg == 0 && i < n) {
+    float t = 0.f;
+    for (int r = 0; r < RED_SEG; ++r) t += s_run[r][o];
+    out[i] = t;
+  }
 }
 
 // dLow[b][y][x][c] = sum of the 2x2 block of dHigh (first `c_low` channels of
@@ -446,7 +462,8 @@ int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st) {
     case 32: hipLaunchKernelGGL(k_wgrad_tiled<32>, grid, dim3(CT), 0, st, a); break;
     default: hipLaunchKernelGGL(k_wgrad_tiled<64>, grid, dim3(CT), 0, st, a); break;
   }
-  hipLaunchKernelGGL(k_reduce_partials, dim3(nblk(n)), dim3(CT), 0, st, a.partial, a.nchunk, n, grad_w_layer);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((n + RED_OUT - 1) / RED_OUT)), dim3(CT), 0, st, a.partial,
+                     a.nchunk, n, grad_w_layer);
   LS_LAUNCH_CHECK();
   return LS_OK;
 }
