@@ -76,6 +76,31 @@ def unet_flops(res: int, pad: int) -> float:
     return float(total)
 
 
+def unet_bytes(res: int, pad: int) -> float:
+    """HBM bytes one tile's BF16 forward must move at least: every layer
+    reads its inputs once and writes its BF16 output once (and the fused 2x2
+    pool output of the two layers that feed a pool); the network input x is
+    FP32, the head reads the crop plus its one-texel halo and writes 4 FP32
+    channels."""
+    R = res + 2 * pad
+    f, h, q = R * R, (R // 2) ** 2, (R // 4) ** 2
+    b16 = 2
+    act = {"A1": 16 * f, "A2": 16 * f, "P1": 16 * h, "A3": 32 * h, "A4": 32 * h, "P2": 32 * q, "A5": 64 * q,
+           "A6": 64 * q, "A7": 32 * h, "A8": 32 * h, "A9": 16 * f, "A10": 16 * f}
+    layers = [  # (inputs, outputs) as activation names; "x" is the FP32 input
+        (["x"], ["A1"]), (["A1"], ["A2", "P1"]), (["P1"], ["A3"]), (["A3"], ["A4", "P2"]), (["P2"], ["A5"]),
+        (["A5"], ["A6"]), (["A6", "A4"], ["A7"]), (["A7"], ["A8"]), (["A8", "A2"], ["A9"]), (["A9"], ["A10"])]
+    total = 0
+    for ins, outs in layers:
+        for t in ins:
+            total += 8 * f * 4 if t == "x" else act[t] * b16
+        for t in outs:
+            total += act[t] * b16
+    halo = (res + 2) ** 2
+    total += halo * 16 * b16 + halo * 8 * 4 + res * res * 4 * 4  # head
+    return float(total)
+
+
 class Timer:
     def __init__(self):
         self.a = torch.cuda.Event(enable_timing=True)
@@ -257,10 +282,14 @@ def main():
     # the convolutions against the matrix-core peak, whatever group dominates
     conv_ms = kernels.get("conv_bf16", {}).get("ms_per_step", 0.0)
     conv_tf = flops_tile * nt / (conv_ms * 1e-3) / 1e12 if conv_ms > 0 else None
+    conv_bytes = unet_bytes(res, g.pad) * nt
+    conv_gbs = conv_bytes / (conv_ms * 1e-3) / 1e9 if conv_ms > 0 else None
     roof_conv = {"kernel": "conv_bf16 (all 11 conv launches of a step)", "bound": "mfma", "achieved": conv_tf,
                  "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                  "frac": conv_tf / PEAK_BF16_TFLOPS if conv_tf else None, "ms_per_step": conv_ms,
-                 "algorithmic_per_step": f"{flops_tile * nt / 1e9:.1f} GFLOP ({flops_tile / 1e9:.4f} GFLOP/tile)"}
+                 "algorithmic_per_step": f"{flops_tile * nt / 1e9:.1f} GFLOP ({flops_tile / 1e9:.4f} GFLOP/tile)",
+                 "hbm_algorithmic_GBps": conv_gbs, "hbm_frac": conv_gbs / PEAK_HBM_GBS if conv_gbs else None,
+                 "hbm_algorithmic_per_step": f"{conv_bytes / 1e9:.2f} GB ({conv_bytes / nt / 1e6:.2f} MB/tile)"}
 
     out = {
         "metric": METRIC,
