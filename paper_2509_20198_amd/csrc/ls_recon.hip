@@ -456,42 +456,65 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
 // broadcast).  A texel keeps the scan's answer when its best squared
 // distance is below the squared distance to every side of the scanned
 // bucket rectangle that faces more buckets (sides rounded inwards by one raw
-// unit); otherwise it falls back to ring_nearest.  Same order on
-// (d^2, v, u), so the result equals ring_nearest's.
+// unit).  While some lane of the wave cannot prove its answer (sparse parts
+// of the window), the rectangle grows by one bucket ring, scanned the same
+// way, up to two rings; a lane still unproven then falls back to
+// ring_nearest.  Same order on (d^2, v, u), so the result equals
+// ring_nearest's.
 __device__ int nearest_block(const Tile& T, int q0, int C, int R, int bi, int bj, int lane, int& qx, int& qy) {
   const int G = T.G;
   const int i = bi * 8 + (lane >> 3), j = bj * 8 + (lane & 7);
+  const bool in_grid = i < R && j < R;
   qx = q0 + j * C;
   qy = q0 + i * C;
   const int i1 = min(bi * 8 + 7, R - 1), j1 = min(bj * 8 + 7, R - 1);
-  const int bx0 = max(bucket_1d(q0 + bj * 8 * C + T.H, G, T.W2) - 1, 0);
-  const int bx1 = min(bucket_1d(q0 + j1 * C + T.H, G, T.W2) + 1, G - 1);
-  const int by0 = max(bucket_1d(q0 + bi * 8 * C + T.H, G, T.W2) - 1, 0);
-  const int by1 = min(bucket_1d(q0 + i1 * C + T.H, G, T.W2) + 1, G - 1);
+  int bx0 = max(bucket_1d(q0 + bj * 8 * C + T.H, G, T.W2) - 1, 0);
+  int bx1 = min(bucket_1d(q0 + j1 * C + T.H, G, T.W2) + 1, G - 1);
+  int by0 = max(bucket_1d(q0 + bi * 8 * C + T.H, G, T.W2) - 1, 0);
+  int by1 = min(bucket_1d(q0 + i1 * C + T.H, G, T.W2) + 1, G - 1);
   int best = -1, bu = 0, bv = 0;
   double bd = 0.0;  // squared distance, exact in double (below 2^36)
-  for (int by = by0; by <= by1; ++by) {
-    const int e = T.boff[by * G + bx1 + 1];
-    for (int p = T.boff[by * G + bx0]; p < e; ++p) {  // buckets bx0..bx1 of a row are contiguous
-      const int2 q = T.uv[p];
-      const double dx = q.x - qx, dy = q.y - qy;
-      const double d = fma(dx, dx, dy * dy);
-      if (best < 0 || d < bd || (d == bd && (q.y < bv || (q.y == bv && q.x < bu)))) {
-        best = p;
-        bd = d;
-        bu = q.x;
-        bv = q.y;
+  // buckets xlo..xhi of rows ylo..yhi (those of a row are contiguous)
+  auto scan = [&](int ylo, int yhi, int xlo, int xhi) {
+    if (xlo > xhi) return;
+    for (int by = ylo; by <= yhi; ++by) {
+      const int e = T.boff[by * G + xhi + 1];
+      for (int p = T.boff[by * G + xlo]; p < e; ++p) {
+        const int2 q = T.uv[p];
+        const double dx = q.x - qx, dy = q.y - qy;
+        const double d = fma(dx, dx, dy * dy);
+        if (best < 0 || d < bd || (d == bd && (q.y < bv || (q.y == bv && q.x < bu)))) {
+          best = p;
+          bd = d;
+          bu = q.x;
+          bv = q.y;
+        }
       }
     }
+  };
+  scan(by0, by1, bx0, bx1);
+  const double fx = qx + T.H, fy = qy + T.H;  // grid-local
+  bool proven = false;
+  for (int ring = 0;; ++ring) {
+    // distance from q to the unscanned buckets
+    double L = 1e300;
+    if (bx0 > 0) L = fmin(L, fx - (ceil(bx0 * T.bw) + 1.0));
+    if (bx1 < G - 1) L = fmin(L, (floor((bx1 + 1) * T.bw) - 1.0) - fx);
+    if (by0 > 0) L = fmin(L, fy - (ceil(by0 * T.bw) + 1.0));
+    if (by1 < G - 1) L = fmin(L, (floor((by1 + 1) * T.bw) - 1.0) - fy);
+    proven = best >= 0 && (L >= 1e300 || (L > 0.0 && bd < L * L));
+    if (ring == 2 || __ballot(in_grid && !proven) == 0) break;
+    const int nx0 = max(bx0 - 1, 0), nx1 = min(bx1 + 1, G - 1), ny0 = max(by0 - 1, 0), ny1 = min(by1 + 1, G - 1);
+    scan(ny0, by0 - 1, nx0, nx1);      // new rows below
+    scan(by1 + 1, ny1, nx0, nx1);      // new rows above
+    scan(by0, by1, nx0, bx0 - 1);      // new columns on the left
+    scan(by0, by1, bx1 + 1, nx1);      // new columns on the right
+    bx0 = nx0;
+    bx1 = nx1;
+    by0 = ny0;
+    by1 = ny1;
   }
-  // distance from q to the unscanned buckets (grid-local coordinates)
-  const double fx = qx + T.H, fy = qy + T.H;
-  double L = 1e300;
-  if (bx0 > 0) L = fmin(L, fx - (ceil(bx0 * T.bw) + 1.0));
-  if (bx1 < G - 1) L = fmin(L, (floor((bx1 + 1) * T.bw) - 1.0) - fx);
-  if (by0 > 0) L = fmin(L, fy - (ceil(by0 * T.bw) + 1.0));
-  if (by1 < G - 1) L = fmin(L, (floor((by1 + 1) * T.bw) - 1.0) - fy);
-  if (best >= 0 && (L >= 1e300 || (L > 0.0 && bd < L * L))) return best;
+  if (proven) return best;
   return ring_nearest(T, qx, qy, -1);
 }
 
