@@ -75,6 +75,14 @@ def test_subset_tile_list_and_pad0():
     _compare(w.region, w.points.numpy(), tl)
 
 
+@pytest.mark.parametrize("n", [9000, 16000])
+def test_dense_tile_points_outside_lds(n):
+    """Windows too dense for the canonical points to fit in LDS (they stay in
+    global memory) and bucket grids near their maximum side."""
+    w = synth.single_tile(seed=n, n=n)
+    _compare(w.region, w.points.numpy(), w.tile_list)
+
+
 def test_pareto_counts_small_tiles():
     counts = synth.counts_pareto(6, 64)
     w = synth.sparse_workload("pareto", 8, 8, counts, 6, order="id")
