@@ -57,6 +57,28 @@ def test_forward_fp32_large_head_pad0():
     assert np.abs(y - y_ref).max() <= 1e-5 * np.abs(y_ref).max()
 
 
+def test_forward_bf16_pad0_every_tiling():
+    """BF16 network on the unpadded grid (planes 64, 32, 16): every forward
+    tiling gives the same bits, within the RMS gate of the FP64 network."""
+    w = synth.batch_tiles(seed=8, tiles_x=3, tiles_y=2, pad=0)
+    xo, cz, st = oracle.recon_tiles(w.region, *w.points.numpy(), w.tile_list)
+    wts = synth.unet_weights(0, bias_std=0.05)
+    results = []
+    try:
+        for c in range(ls.conv_num_configs(0, ls.BF16, 0)):
+            for layer in range(len(synth.UNET_SHAPES)):
+                ls.set_conv_config(layer, ls.BF16, 0, c)
+            results.append(_run(w, xo, cz, wts, ls.BF16))
+    finally:
+        for layer in range(len(synth.UNET_SHAPES)):
+            ls.set_conv_config(layer, ls.BF16, 0, -1)
+    for y, tex in results[1:]:
+        assert np.array_equal(y, results[0][0]) and np.array_equal(tex, results[0][1])
+    y_ref = oracle.unet_forward(wts, xo, 64, 0)
+    tex_ref = oracle.texture(y_ref, cz, w.region)
+    assert rms_per_tile(results[0][1][..., 0], tex_ref[..., 0]).max() <= 0.05
+
+
 def test_zero_head_is_linear_baseline():
     w, xo, cz = _x_from_oracle(2)
     wts = synth.unet_weights(0)
