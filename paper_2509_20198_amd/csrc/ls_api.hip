@@ -67,8 +67,9 @@ int ls_conv_num_configs_impl(int layer, int precision, int pass) {
   //   3 = LDS tile in persistent workgroups prefetching the next patch
   // BF16 input gradient: 0 / 1 = direct with 4 / 2 pixel tiles per wave
   // FP32 conv (forward, input gradient): 0..3 = channel block cap 32, 16, 8, 4
-  // weight gradient (both precisions): 0..2 = 512, 256, 128 pixel chunks
-  if (pass == 2) return 3;
+  // weight gradient (both precisions): 0..2 = 512, 256, 128 pixel chunks;
+  //   BF16 also 3..5 = the same on the matrix cores
+  if (pass == 2) return precision == LS_BF16 ? 6 : 3;
   if (precision == LS_BF16) return pass == 0 ? 4 : 2;
   return 4;
 }

@@ -180,6 +180,7 @@ int wgrad(const ConvSrc& s, int B, int H, int l, const float* dA, const float* m
   a.d_stride = d_stride;
   a.round_in = 0;
   a.partial = partial;
+  a.mfma = 0;
   const int64_t npix = (int64_t)B * Ho * Wo;
   const int chunks = ls_wgrad_chunks_for_config(ls_conv_config_get(l, LS_FP32, 2));
   a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, npix / 256));
@@ -206,8 +207,10 @@ int wgrad_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* g, int d_s
   a.d_stride = d_stride;
   a.round_in = 1;
   a.partial = partial;
+  const int cfg = ls_conv_config_get(l, LS_BF16, 2);
+  a.mfma = (cfg < 0 || cfg >= 3) ? 1 : 0;  // default: the matrix cores
   const int64_t npix = (int64_t)B * Ho * Wo;
-  const int chunks = ls_wgrad_chunks_for_config(ls_conv_config_get(l, LS_BF16, 2));
+  const int chunks = ls_wgrad_chunks_for_config(cfg);
   a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, npix / 256));
   return ls_wgrad_f32(a, grad_w + ls_layer_w_offset(l), st);
 }

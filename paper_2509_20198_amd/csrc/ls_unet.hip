@@ -293,6 +293,180 @@ __global__ void __launch_bounds__(CT) k_wgrad_tiled(WgradArgs A) {
   }
 }
 
+// The same dW partials on the matrix cores for the BF16 path (gradient
+// already masked and rounded to BF16, inputs rounded to BF16):
+// D[co][n] += A[co][32 pixels] * B[32 pixels][n] per
+// v_mfma_f32_16x16x32_bf16, FP32 accumulation.  A 32-pixel slab is staged in
+// LDS pixel-contiguous (transposed: one row of 32 pixels per channel and per
+// im2col column), so every A and B fragment (8 consecutive pixels of one
+// row) is a single 16-byte read; rows are 80 bytes apart, which keeps the 16
+// rows of a fragment in distinct banks.  Wave w owns column tiles
+// [w * CTW, (w + 1) * CTW) of the workgroup's 64 * CTW columns for all
+// channel tiles; the bias is the column of ones n = 9 * cin.
+constexpr int WM_PITCH = 40;  // BF16 elements per staged row (32 pixels + pad)
+typedef __bf16 wm_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float wm_f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short wm_u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint32_t wm_pack(float lo, float hi) {
+  return (uint32_t)__builtin_bit_cast(unsigned short, static_cast<__bf16>(lo)) |
+         ((uint32_t)__builtin_bit_cast(unsigned short, static_cast<__bf16>(hi)) << 16);
+}
+
+// channels cc..cc+7 of part p at input-plane pixel (yy, xx) as BF16 bits
+// (FP32-stored parts rounded to nearest even); zero outside
+__device__ __forceinline__ uint4 wm_load8(const SrcPart& p, int b, int yy, int xx, int cc, int H, int W) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  if (yy < 0 || xx < 0 || yy >= H || xx >= W) return z;
+  int sy, sx;
+  if (p.up) {
+    sy = yy >> 1;
+    sx = xx >> 1;
+  } else {
+    sy = yy - p.oy;
+    sx = xx - p.ox;
+  }
+  if (sy < 0 || sx < 0 || sy >= p.h || sx >= p.w) return z;
+  const int64_t o = (((int64_t)b * p.h + sy) * p.w + sx) * p.stride + p.coff + cc;
+  if (p.bf16) return *reinterpret_cast<const uint4*>(p.bf16 + o);
+  const float4 f0 = *reinterpret_cast<const float4*>(p.f32 + o);
+  const float4 f1 = *reinterpret_cast<const float4*>(p.f32 + o + 4);
+  return make_uint4(wm_pack(f0.x, f0.y), wm_pack(f0.z, f0.w), wm_pack(f1.x, f1.y), wm_pack(f1.z, f1.w));
+}
+
+template <int MT, int CTW>
+__global__ void __launch_bounds__(CT) k_wgrad_mfma(WgradArgs A) {
+  constexpr int COLS = 4 * CTW * 16;
+  constexpr int NJ = COLS / 128;  // column octets a thread stages per slab
+  __shared__ __align__(16) uint16_t s_g[MT * 16][WM_PITCH];
+  __shared__ __align__(16) uint16_t s_x[COLS][WM_PITCH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int cin = A.src.a.c + A.src.b.c;
+  const int N = 9 * cin;
+  const int nb = blockIdx.x * COLS;
+  const int64_t npix = (int64_t)A.B * A.Ho * A.Wo;
+  const int64_t p0 = npix * blockIdx.y / gridDim.y, p1 = npix * (blockIdx.y + 1) / gridDim.y;
+  // A thread always stages the same pixel pair of a slab and the same
+  // column octets, so their decoding is done once: column octet j is an
+  // input octet (tap ky, kx; part; channel), the bias octet, or zero.
+  const int pp = tid & 15;
+  int cdesc[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int n = nb + 8 * ((tid >> 4) + 16 * j);
+    if (n < N) {
+      const int tap = n / cin, ci = n - tap * cin;
+      const int ky = tap / 3, kx = tap - 3 * ky;
+      const bool in_a = ci < A.src.a.c;
+      cdesc[j] = (in_a ? 0 : (1 << 24)) | (ky << 20) | (kx << 18) | (in_a ? ci : ci - A.src.a.c);
+    } else {
+      cdesc[j] = n == N ? (2 << 24) : (3 << 24);
+    }
+  }
+  // output pixel (b, oy, ox) of the pair's two pixels, advanced slab by slab
+  int pb[2], py[2], px[2];
+  const int64_t hw = (int64_t)A.Ho * A.Wo;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t p = p0 + 2 * pp + h;
+    pb[h] = (int)(p / hw);
+    const int r = (int)(p - (int64_t)pb[h] * hw);
+    py[h] = r / A.Wo;
+    px[h] = r - py[h] * A.Wo;
+  }
+  wm_f32x4 acc[MT][CTW];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) acc[mt][ct] = wm_f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t ps = p0; ps < p1; ps += 32) {
+    // gradient: thread = (pixel pair, 4 channels)
+    for (int e = tid; e < 16 * MT * 4; e += CT) {
+      const int cq = e >> 4;
+      uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
+      if (4 * cq < A.cout) {
+        const int64_t pa = ps + 2 * pp;
+        if (pa < p1) v0 = *reinterpret_cast<const uint2*>(A.g_bf16 + pa * A.d_stride + 4 * cq);
+        if (pa + 1 < p1) v1 = *reinterpret_cast<const uint2*>(A.g_bf16 + (pa + 1) * A.d_stride + 4 * cq);
+      }
+      uint32_t* row = reinterpret_cast<uint32_t*>(&s_g[4 * cq][2 * pp]);
+      row[0 * WM_PITCH / 2] = (v0.x & 0xFFFFu) | (v1.x << 16);
+      row[1 * WM_PITCH / 2] = (v0.x >> 16) | (v1.x & 0xFFFF0000u);
+      row[2 * WM_PITCH / 2] = (v0.y & 0xFFFFu) | (v1.y << 16);
+      row[3 * WM_PITCH / 2] = (v0.y >> 16) | (v1.y & 0xFFFF0000u);
+    }
+    // im2col columns: thread = (pixel pair, 8 columns of one tap)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int co8 = (tid >> 4) + 16 * j;
+      const int d = cdesc[j], kind = d >> 24;
+      uint4 v[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        v[h] = make_uint4(0u, 0u, 0u, 0u);
+        if (ps + 2 * pp + h < p1) {
+          if (kind < 2) {
+            const int ky = (d >> 20) & 3, kx = (d >> 18) & 3, cc = d & 0x3FFFF;
+            v[h] = wm_load8(kind == 0 ? A.src.a : A.src.b, pb[h], A.y0 + py[h] + ky - 1, A.x0 + px[h] + kx - 1, cc,
+                            A.H, A.W);
+          } else if (kind == 2) {
+            v[h].x = 0x3F80u;  // BF16 1.0 in column N
+          }
+        }
+      }
+      uint32_t* row = reinterpret_cast<uint32_t*>(&s_x[8 * co8][2 * pp]);
+      const uint32_t a0[4] = {v[0].x, v[0].y, v[0].z, v[0].w}, a1[4] = {v[1].x, v[1].y, v[1].z, v[1].w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        row[(2 * c) * WM_PITCH / 2] = (a0[c] & 0xFFFFu) | (a1[c] << 16);
+        row[(2 * c + 1) * WM_PITCH / 2] = (a0[c] >> 16) | (a1[c] & 0xFFFF0000u);
+      }
+    }
+    __syncthreads();
+    wm_bf16x8 af[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      af[mt] = __builtin_bit_cast(wm_bf16x8, *reinterpret_cast<const wm_u16x8*>(&s_g[mt * 16 + r16][8 * g]));
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) {
+      const wm_bf16x8 bf =
+          __builtin_bit_cast(wm_bf16x8, *reinterpret_cast<const wm_u16x8*>(&s_x[(wave * CTW + ct) * 16 + r16][8 * g]));
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bf, acc[mt][ct], 0, 0, 0);
+    }
+    // next slab: advance both pixels by 32 (rows of any width, images)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      px[h] += 32;
+      while (px[h] >= A.Wo) {
+        px[h] -= A.Wo;
+        if (++py[h] == A.Ho) {
+          py[h] = 0;
+          ++pb[h];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  float* out = A.partial + (int64_t)blockIdx.y * ((int64_t)A.cout * N + A.cout);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int ct = 0; ct < CTW; ++ct) {
+      const int n = nb + (wave * CTW + ct) * 16 + r16;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = mt * 16 + 4 * g + i;
+        if (co >= A.cout) continue;
+        if (n < N)
+          out[(int64_t)co * N + n] = acc[mt][ct][i];
+        else if (n == N)
+          out[(int64_t)A.cout * N + co] = acc[mt][ct][i];
+      }
+    }
+}
+
 // out[i] = sum over chunks of partial[c][i], in a fixed order: RED_SEG
 // consecutive runs of chunks are summed in parallel (each run in chunk
 // order), then the run sums in run order.  A workgroup covers RED_OUT
@@ -454,13 +628,32 @@ int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st) {
   if (a.cout % 4 || a.src.a.c % 4 || a.src.b.c % 4 || a.d_stride % 4) return LS_ENOTIMPL;
   const int mwg = a.cout <= 16 ? 16 : (a.cout <= 32 ? 32 : 64);
   if (a.cout > 64) return LS_ENOTIMPL;
-  const int cols = 4 * (CT / (mwg / 4));
-  dim3 grid((unsigned)((9 * cin + 1 + cols - 1) / cols), (unsigned)a.nchunk);
   LS_TRACE("wgrad", st);
-  switch (mwg) {
-    case 16: hipLaunchKernelGGL(k_wgrad_tiled<16>, grid, dim3(CT), 0, st, a); break;
-    case 32: hipLaunchKernelGGL(k_wgrad_tiled<32>, grid, dim3(CT), 0, st, a); break;
-    default: hipLaunchKernelGGL(k_wgrad_tiled<64>, grid, dim3(CT), 0, st, a); break;
+  // the matrix-core kernel stages 8 channels of one part at a time
+  if (a.mfma && a.g_bf16 && a.src.a.c % 8 == 0 && a.src.b.c % 8 == 0) {
+    // column tiles per wave: the fewest that cover the columns in one
+    // workgroup, at most 8 (more workgroups along x beyond that)
+    const int tiles = (9 * cin + 1 + 15) / 16;
+    const int ctw = tiles <= 8 ? 2 : (tiles <= 16 ? 4 : 8);
+    dim3 grid((unsigned)((9 * cin + 1 + 64 * ctw - 1) / (64 * ctw)), (unsigned)a.nchunk);
+#define LS_WM(M, C) hipLaunchKernelGGL((k_wgrad_mfma<M, C>), grid, dim3(CT), 0, st, a)
+    const int mt = (a.cout + 15) / 16;
+    if (mt == 1) {
+      if (ctw == 2) LS_WM(1, 2); else if (ctw == 4) LS_WM(1, 4); else LS_WM(1, 8);
+    } else if (mt == 2) {
+      if (ctw == 2) LS_WM(2, 2); else if (ctw == 4) LS_WM(2, 4); else LS_WM(2, 8);
+    } else {
+      if (ctw == 2) LS_WM(4, 2); else if (ctw == 4) LS_WM(4, 4); else LS_WM(4, 8);
+    }
+#undef LS_WM
+  } else {
+    const int cols = 4 * (CT / (mwg / 4));
+    dim3 grid((unsigned)((9 * cin + 1 + cols - 1) / cols), (unsigned)a.nchunk);
+    switch (mwg) {
+      case 16: hipLaunchKernelGGL(k_wgrad_tiled<16>, grid, dim3(CT), 0, st, a); break;
+      case 32: hipLaunchKernelGGL(k_wgrad_tiled<32>, grid, dim3(CT), 0, st, a); break;
+      default: hipLaunchKernelGGL(k_wgrad_tiled<64>, grid, dim3(CT), 0, st, a); break;
+    }
   }
   hipLaunchKernelGGL(k_reduce_partials, dim3((unsigned)((n + RED_OUT - 1) / RED_OUT)), dim3(CT), 0, st, a.partial,
                      a.nchunk, n, grad_w_layer);

@@ -46,14 +46,19 @@ struct WgradArgs {
   int round_in;             // round FP32-stored inputs to BF16 (BF16 path)
   float* partial;           // [nchunk][cout*9*cin + cout]
   int nchunk;
+  int mfma;                 // BF16 gradient only: the matrix-core kernel
 };
 
 // Tiling choices per (layer, precision, pass), set by ls_set_conv_config.
 int ls_conv_config_get(int layer, int precision, int pass);
 // FP32 conv: config 0..3 -> channel block cap 32, 16, 8, 4
 inline int ls_cob_for_config(int c) { return c <= 0 ? 32 : (c == 1 ? 16 : (c == 2 ? 8 : 4)); }
-// weight gradient: config 0..2 -> pixel chunks 512, 256, 128
-inline int ls_wgrad_chunks_for_config(int c) { return c <= 0 ? 512 : (c == 1 ? 256 : 128); }
+// weight gradient: config 0..2 -> pixel chunks 512, 256, 128 (vector FP32
+// products); BF16 also 3..5 -> the same chunk counts on the matrix cores
+inline int ls_wgrad_chunks_for_config(int c) {
+  const int k = c < 0 ? 0 : c % 3;
+  return k == 0 ? 512 : (k == 1 ? 256 : 128);
+}
 
 SrcPart src_plain(const float* p, int c, int h, int w, int stride, int coff, const float* mask);
 SrcPart src_none();
