@@ -159,7 +159,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-tiles", type=int, default=64, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-tiles", type=int, default=256, help="oracle sample size (0 = skip)")
     ap.add_argument("--no-secondary", action="store_true", help="skip splat / backward figures")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward / training figures")
     ap.add_argument("--copy-calibration", action="store_true",
