@@ -43,6 +43,8 @@ constexpr int MAXB = MAXG * MAXG;        // max buckets
 static_assert(2 * (MAXB + 1) <= LDS_INTS, "bucket offsets must fit twice in the recon LDS");
 constexpr int STAR_MAX_STEPS = 1024;     // safeguard on one point's star walk
 constexpr uint64_t FACE_NONE = ~0ull;
+constexpr int SUCC_K = 8;                // cached star successors per point
+constexpr uint64_t SUCC_EMPTY = ~0ull;
 constexpr int SORT_LDS = 16384;          // bin segments up to this size sort in LDS
 
 struct BinParams {
@@ -312,6 +314,8 @@ struct ReconParams {
   uint64_t* trgb;
   int2* cuv;
   uint64_t* tris;  // 2 entries per bin entry: large triangles of a tile, rasterised after its stars
+  uint64_t* succ;  // SUCC_K entries per bin entry: known star successors (key << 32 | third vertex)
+  int32_t* succ_n;  // per bin entry: successor entries claimed
   // per workgroup scratch
   uint64_t* facemap;  // [gridDim][R*R]
   int32_t* nnidx;     // [gridDim][R*R]
@@ -1105,15 +1109,51 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
         raster_triangle(T, p, q, r, C, R, fm);
       };
       if (has_dt) {
-        // nearest neighbour of every point: the first edge of its star
+        // nearest neighbour of every point: the first edge of its star;
+        // successor lists cleared
         int32_t* __restrict__ nb0 = P.sslot + off;
-        for (int a = tid; a < m; a += RB) nb0[a] = ring_nearest(T, T.uv[a].x, T.uv[a].y, a);
+        uint64_t* __restrict__ succ = P.succ + (int64_t)off * SUCC_K;
+        int32_t* __restrict__ succ_n = P.succ_n + off;
+        for (int a = tid; a < m; a += RB) {
+          nb0[a] = ring_nearest(T, T.uv[a].x, T.uv[a].y, a);
+          succ_n[a] = 0;
+          ulonglong2* s2 = reinterpret_cast<ulonglong2*>(succ + (int64_t)a * SUCC_K);
+#pragma unroll
+          for (int j = 0; j < SUCC_K / 2; ++j) s2[j] = make_ulonglong2(SUCC_EMPTY, SUCC_EMPTY);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
-        // Each lane walks one star at a time, one third-vertex search per
-        // iteration, and takes the next point from a shared counter as soon
-        // as its star is done, so the lanes of a wave are not held at star
-        // boundaries.  The walk turns counter-clockwise from the nearest
-        // neighbour b0; if it meets the hull it resumes clockwise from b0.
+        // Every triangle lies in the stars of its three vertices.  A search
+        // that finds triangle (p, q, c) left of p->q also answers the
+        // searches left of q->c (third vertex p) and c->p (third vertex q);
+        // it records them in the successor lists of q and c, keyed by the
+        // edge's second vertex.  The search is exact, so a recorded answer
+        // is the answer the search would give.
+        auto succ_find = [&](int p, int q) -> int {
+          const uint64_t* l = succ + (int64_t)p * SUCC_K;
+          uint64_t v[SUCC_K];
+#pragma unroll
+          for (int j = 0; j < SUCC_K; ++j) v[j] = __hip_atomic_load(l + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          int c = -1;
+#pragma unroll
+          for (int j = 0; j < SUCC_K; ++j)
+            if (v[j] != SUCC_EMPTY && (int)(v[j] >> 32) == q) c = (int)(uint32_t)v[j];
+          return c;
+        };
+        auto succ_put = [&](int p, int q, int c) {
+          const int j = __hip_atomic_fetch_add(succ_n + p, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (j < SUCC_K)
+            __hip_atomic_store(succ + (int64_t)p * SUCC_K + j, ((uint64_t)(uint32_t)q << 32) | (uint32_t)c,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        };
+        // Each lane walks one star at a time and takes the next point from a
+        // shared counter as soon as its star is done, so the lanes of a wave
+        // are not held at star boundaries.  The walk turns counter-clockwise
+        // from the nearest neighbour b0; if it meets the hull it resumes
+        // clockwise from b0.  Steps whose answer is already recorded are
+        // taken at once; a wave searches only when none of its lanes can
+        // step from the lists, and then all its waiting lanes search
+        // together.
         int a = atomicAdd(&s_next, 1);
         int b0 = 0, b = 0, steps = 0, prev_b = -1, hull_b = -1;
         bool back = false, first = true;
@@ -1129,38 +1169,54 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
           hull_key = FACE_NONE;
         };
         if (a < m) start();
-        while (a < m) {
+        // one step with c the third vertex left of the current edge (-1: none)
+        auto advance = [&](int c) {
+          // forward: triangle (a, b, c) left of a->b; backward: (b, a, c)
+          const int p = back ? b : a, q = back ? a : b;
           bool done = false;
-          if (steps++ >= STAR_MAX_STEPS) {
+          if (c < 0) {
+            if (back) {
+              done = true;
+            } else {
+              hull_b = b;
+              if (prev_b >= 0) hull_key = face_key(a, prev_b, b);
+              back = true;
+              b = b0;
+            }
+          } else {
+            if (back && first && hull_key == FACE_NONE) hull_key = face_key(p, q, c);
+            if (back) first = false;
+            if (a < b && a < c) emit(p, q, c);
+            prev_b = b;
+            b = c;
+            if (!back && b == b0) done = true;
+          }
+          if (!done && ++steps >= STAR_MAX_STEPS) {
             atomicOr(&s_flags, LS_TILE_DEGENERATE);
             done = true;
-          } else {
-            // forward: triangle (a, b, c) left of a->b; backward: (b, a, c)
-            const int p = back ? b : a, q = back ? a : b;
-            const int c = third_left(T, p, q);
-            if (c < 0) {
-              if (back) {
-                done = true;
-              } else {
-                hull_b = b;
-                if (prev_b >= 0) hull_key = face_key(a, prev_b, b);
-                back = true;
-                b = b0;
-              }
-            } else {
-              if (back && first && hull_key == FACE_NONE) hull_key = face_key(p, q, c);
-              if (back) first = false;
-              if (a < b && a < c) emit(p, q, c);
-              prev_b = b;
-              b = c;
-              if (!back && b == b0) done = true;
-            }
           }
           if (done) {
             if (hull_b >= 0 && hull_key != FACE_NONE) raster_hull_edge(T, a, hull_b, hull_key, C, R, fm);
             a = atomicAdd(&s_next, 1);
             if (a < m) start();
           }
+        };
+        for (;;) {
+          const bool live = a < m;
+          if (__ballot(live) == 0) break;
+          const int p = back ? b : a, q = back ? a : b;
+          int c = live ? succ_find(p, q) : -1;
+          const bool hit = c >= 0;
+          bool step = hit;
+          if (__ballot(hit) == 0 && live) {
+            c = third_left(T, p, q);
+            if (c >= 0) {
+              succ_put(q, c, p);
+              succ_put(c, p, q);
+            }
+            step = true;
+          }
+          if (step) advance(c);
         }
       }
       __syncthreads();
@@ -1258,6 +1314,8 @@ struct ReconLayout {
   uint64_t *srgb, *trgb;
   int2* cuv;
   uint64_t* tris;
+  uint64_t* succ;
+  int32_t* succ_n;
   uint64_t* facemap;
   int32_t* nnidx;
   int n_wg;
@@ -1300,6 +1358,8 @@ size_t recon_layout(const LsGridInfo& gi, int32_t n_tiles, int64_t n, void* base
   L->trgb = A.take<uint64_t>(E);
   L->cuv = A.take<int2>(E);
   L->tris = A.take<uint64_t>(2 * E);
+  L->succ = A.take<uint64_t>(SUCC_K * E);
+  L->succ_n = A.take<int32_t>(E);
   L->facemap = A.take<uint64_t>(RR * nwg);
   L->nnidx = A.take<int32_t>(RR * nwg);
   L->n_wg = nwg;
@@ -1428,6 +1488,8 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   rp.trgb = L.trgb;
   rp.cuv = L.cuv;
   rp.tris = L.tris;
+  rp.succ = L.succ;
+  rp.succ_n = L.succ_n;
   rp.facemap = L.facemap;
   rp.nnidx = L.nnidx;
   rp.queue = L.queue;
