@@ -45,6 +45,7 @@ constexpr int STAR_MAX_STEPS = 1024;     // safeguard on one point's star walk
 constexpr uint64_t FACE_NONE = ~0ull;
 constexpr int SUCC_K = 8;                // cached star successors per point
 constexpr uint64_t SUCC_EMPTY = ~0ull;
+constexpr int SEARCH_MAX_HITS = 12;      // a wave searches once at most this many lanes can step from the lists
 constexpr int SORT_LDS = 16384;          // bin segments up to this size sort in LDS
 
 struct BinParams {
@@ -1151,7 +1152,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
         // are not held at star boundaries.  The walk turns counter-clockwise
         // from the nearest neighbour b0; if it meets the hull it resumes
         // clockwise from b0.  Steps whose answer is already recorded are
-        // taken at once; a wave searches only when none of its lanes can
+        // taken at once; a wave searches only when few of its lanes can
         // step from the lists, and then all its waiting lanes search
         // together.
         int a = atomicAdd(&s_next, 1);
@@ -1208,7 +1209,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
           int c = live ? succ_find(p, q) : -1;
           const bool hit = c >= 0;
           bool step = hit;
-          if (__ballot(hit) == 0 && live) {
+          if (__popcll(__ballot(hit)) <= SEARCH_MAX_HITS && live && !hit) {
             c = third_left(T, p, q);
             if (c >= 0) {
               succ_put(q, c, p);
