@@ -187,6 +187,29 @@ def test_near_collinear_band():
              np.zeros(1, np.int32))
 
 
+@pytest.mark.parametrize("k", [16, 30, 48])
+def test_high_degree_wheels(k):
+    """Hubs ringed by k points on a circle: each hub has k Delaunay
+    neighbours (more than a star successor list holds) and the ring points
+    are nearly cocircular, so recorded and searched steps mix with the exact
+    fallbacks of the predicates."""
+    region = synth.Region()
+    rng = np.random.default_rng(k)
+    H = 48000
+    hubs = rng.integers(-H + 8000, H - 8000, (5, 2))
+    u, v = [], []
+    for hx, hy in hubs:
+        r = int(rng.integers(2000, 5000))
+        t = 2 * np.pi * (np.arange(k) + rng.uniform(0, 1)) / k
+        u += [hx] + list(np.rint(hx + r * np.cos(t)).astype(np.int64))
+        v += [hy] + list(np.rint(hy + r * np.sin(t)).astype(np.int64))
+    bu, bv = rng.integers(-H, H, 600), rng.integers(-H, H, 600)
+    far = np.min(np.hypot(bu[:, None] - hubs[None, :, 0], bv[:, None] - hubs[None, :, 1]), axis=1) > 7500
+    u = np.concatenate([u, bu[far], [-H, H - 1, -H, H - 1]])
+    v = np.concatenate([v, bv[far], [-H, -H, H - 1, H - 1]])
+    _compare(region, _window_points(u, v, rng), np.zeros(1, np.int32))
+
+
 def test_deterministic_and_order_independent():
     w = synth.batch_tiles(seed=11, tiles_x=4, tiles_y=4)
     ps = w.points.numpy()
