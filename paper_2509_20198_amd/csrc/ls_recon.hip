@@ -15,8 +15,7 @@
 //           them into a G x G grid over the window (LDS counting sort);
 //        b. sort each bucket by (v, u) and drop duplicate positions,
 //           keeping the largest (z, R, G, B) -> canonical points;
-//        c. nearest point of every texel centre (exact int64 distances,
-//           ties by (d^2, v, u)) by ring search over the buckets;
+//        c. face map reset;
 //        d. Delaunay triangulation: every point computes its own star by
 //           gift-wrapping (first point hit by a circle growing from a
 //           Delaunay edge), with exact orientation and in-circle tests and a
@@ -25,7 +24,9 @@
 //           when points are cocircular.  A triangle is rasterised by its
 //           lowest-index vertex into a per-texel face map (top-left rule),
 //           hull edges by one endpoint, so every texel of the closed convex
-//           hull gets a containing triangle;
+//           hull gets a containing triangle.  Waves whose walks are done go
+//           on to the nearest point of every texel centre (exact distances,
+//           ties by (d^2, v, u)) by scans over the buckets;
 //        e. c_z from the centre texel, then per texel: barycentric height and
 //           colour inside the hull, nearest point outside it (the paper's
 //           corner padding points taken at infinity), normalised and written
@@ -930,6 +931,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
   __shared__ int s_flags;
   __shared__ int s_ntri;
   __shared__ int s_next;
+  __shared__ int s_nnblk;
   __shared__ double s_cz;
   const int tid = threadIdx.x;
   const int R = P.R, C = P.C, H = P.H, W2 = 2 * P.H;
@@ -988,6 +990,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
         s_flags = 0;
         s_ntri = 0;
         s_next = 0;
+        s_nnblk = 0;
       }
       __syncthreads();
       for (int e = tid; e < cnt; e += RB) {
@@ -1065,21 +1068,9 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       T.bw = (double)W2 / G;
       const int32_t* Tz = P.sz + off;
       const uint64_t* Tc = P.srgb + off;
-      // ---- c. nearest point per texel; face map reset
+      // ---- c. face map reset (the nearest points follow the stars)
       const int q0 = -H + C / 2;
-      {
-        const int nbs = (R + 7) / 8, lane = tid & 63;
-        for (int blk = tid >> 6; blk < nbs * nbs; blk += RB / 64) {
-          const int bi = blk / nbs, bj = blk - bi * nbs;
-          int qx, qy;
-          const int b = nearest_block(T, q0, C, R, bi, bj, lane, qx, qy);
-          const int i = bi * 8 + (lane >> 3), j = bj * 8 + (lane & 7);
-          if (i < R && j < R) {
-            nn[i * R + j] = b;
-            fm[i * R + j] = FACE_NONE;
-          }
-        }
-      }
+      for (int tt = tid; tt < RR; tt += RB) fm[tt] = FACE_NONE;
       // collinearity check
       bool noncol = false;
       if (m >= 3) {
@@ -1218,6 +1209,23 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
             step = true;
           }
           if (step) advance(c);
+        }
+      }
+      // nearest point per texel: 8 x 8 texel blocks taken from a shared
+      // counter by each wave once its star walks are done, so the waves
+      // that finish early fill the tail of the star phase
+      {
+        const int nbs = (R + 7) / 8, lane = tid & 63;
+        for (;;) {
+          int blk = 0;
+          if (lane == 0) blk = atomicAdd(&s_nnblk, 1);
+          blk = __builtin_amdgcn_readfirstlane(__shfl(blk, 0));
+          if (blk >= nbs * nbs) break;
+          const int bi = blk / nbs, bj = blk - bi * nbs;
+          int qx, qy;
+          const int b = nearest_block(T, q0, C, R, bi, bj, lane, qx, qy);
+          const int i = bi * 8 + (lane >> 3), j = bj * 8 + (lane & 7);
+          if (i < R && j < R) nn[i * R + j] = b;
         }
       }
       __syncthreads();
