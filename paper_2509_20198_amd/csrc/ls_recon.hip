@@ -813,13 +813,15 @@ __device__ __forceinline__ bool tri_texel_box(const Tile& T, int a, int b, int c
 }
 
 // Triangles whose texel box exceeds this many texels are rasterised after
-// the star phase by a whole wave (one lane per texel of the box), so a few
-// large triangles do not hold up the lanes of a wave that walk their stars.
+// the star phase by a group of RASTER_LANES lanes (one lane per texel of the
+// box), so a few large triangles do not hold up the lanes of a wave that
+// walk their stars.
 constexpr int WAVE_RASTER_TEXELS = 8;
+constexpr int RASTER_LANES = 16;
 
-// raster_triangle's result, computed by the 64 lanes of a wave: every texel
-// of the box gets the exact top-left test.
-__device__ void raster_triangle_wave(const Tile& T, uint64_t key, int C, int R, uint64_t* __restrict__ fm, int lane) {
+// raster_triangle's result, computed by the RASTER_LANES lanes of a group:
+// every texel of the box gets the exact top-left test.
+__device__ void raster_triangle_group(const Tile& T, uint64_t key, int C, int R, uint64_t* __restrict__ fm, int lane) {
   const int a = (int)(key >> 42), b = (int)((key >> 21) & 0x1FFFFF), c = (int)(key & 0x1FFFFF);
   int i0, i1, j0, j1;
   if (!tri_texel_box(T, a, b, c, C, R, i0, i1, j0, j1)) return;
@@ -829,7 +831,7 @@ __device__ void raster_triangle_wave(const Tile& T, uint64_t key, int C, int R, 
   const int q0 = -T.H + C / 2;
   const int w = j1 - j0 + 1, n = (i1 - i0 + 1) * w;
   const float rw = __builtin_amdgcn_rcpf((float)w);
-  for (int e = lane; e < n; e += 64) {
+  for (int e = lane; e < n; e += RASTER_LANES) {
     // e / w from a float estimate (e < 2^14), corrected exactly
     int di = (int)((float)e * rw);
     if (di * w > e)
@@ -1086,7 +1088,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       // ---- d. Delaunay stars, rasterised into the face map
       uint64_t* __restrict__ tris = P.tris + 2 * (int64_t)off;
       // a small triangle is rasterised by its lane at once, a large one is
-      // queued for the wave pass below (or rasterised at once if the queue,
+      // queued for the group pass below (or rasterised at once if the queue,
       // sized for the 2m - 5 triangles of a triangulation, is full)
       auto emit = [&](int p, int q, int r) {
         int i0, i1, j0, j1;
@@ -1231,7 +1233,8 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       __syncthreads();
       {
         const int ntri = min(__builtin_amdgcn_readfirstlane(s_ntri), 2 * cnt);
-        for (int t = tid >> 6; t < ntri; t += RB / 64) raster_triangle_wave(T, tris[t], C, R, fm, tid & 63);
+        for (int t = tid / RASTER_LANES; t < ntri; t += RB / RASTER_LANES)
+          raster_triangle_group(T, tris[t], C, R, fm, tid % RASTER_LANES);
       }
       __syncthreads();
       // ---- e. interpolation, normalisation, output
