@@ -812,12 +812,11 @@ __device__ __forceinline__ bool tri_texel_box(const Tile& T, int a, int b, int c
   return i0 <= i1 && j0 <= j1;
 }
 
-// Triangles whose texel box exceeds this many texels are rasterised after
-// the star phase by a group of RASTER_LANES lanes (one lane per texel of the
-// box), so a few large triangles do not hold up the lanes of a wave that
-// walk their stars.
-constexpr int WAVE_RASTER_TEXELS = 8;
-constexpr int RASTER_LANES = 16;
+// Triangles are rasterised after the star phase by groups of RASTER_LANES
+// lanes (one lane per texel of the box), not by the lane that finds them, so
+// rasterisation neither holds up the lanes of a wave that walk their stars
+// nor diverges with the box sizes.
+constexpr int RASTER_LANES = 8;
 
 // raster_triangle's result, computed by the RASTER_LANES lanes of a group:
 // every texel of the box gets the exact top-left test.
@@ -1087,18 +1086,16 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       if (m >= (1 << 21) && tid == 0) atomicOr(&s_flags, LS_TILE_DEGENERATE);
       // ---- d. Delaunay stars, rasterised into the face map
       uint64_t* __restrict__ tris = P.tris + 2 * (int64_t)off;
-      // a small triangle is rasterised by its lane at once, a large one is
-      // queued for the group pass below (or rasterised at once if the queue,
-      // sized for the 2m - 5 triangles of a triangulation, is full)
+      // a triangle that covers a texel centre is queued for the group pass
+      // below (or rasterised at once if the queue, sized for the 2m - 5
+      // triangles of a triangulation, is full)
       auto emit = [&](int p, int q, int r) {
         int i0, i1, j0, j1;
         if (!tri_texel_box(T, p, q, r, C, R, i0, i1, j0, j1)) return;
-        if ((i1 - i0 + 1) * (j1 - j0 + 1) > WAVE_RASTER_TEXELS) {
-          const int slot = atomicAdd(&s_ntri, 1);
-          if (slot < 2 * cnt) {
-            tris[slot] = face_key(p, q, r);
-            return;
-          }
+        const int slot = atomicAdd(&s_ntri, 1);
+        if (slot < 2 * cnt) {
+          tris[slot] = face_key(p, q, r);
+          return;
         }
         raster_triangle(T, p, q, r, C, R, fm);
       };
