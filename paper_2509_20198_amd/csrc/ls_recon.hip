@@ -926,7 +926,7 @@ __device__ __forceinline__ void write_zero_tile(const ReconParams& P, int k) {
 __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
   // region 0 holds the raw bucket offsets while bucketing, then the
   // canonical coordinates; the canonical bucket offsets sit at the end
-  __shared__ int s_mem[LDS_INTS];
+  __shared__ __align__(16) int s_mem[LDS_INTS];
   __shared__ int s_tmp[RB / 64 + 1];
   __shared__ int s_hdr[5];  // tile index, flags, bin offset, bin count, tile id
   __shared__ int s_flags;
@@ -1007,55 +1007,73 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       }
       __syncthreads();
       block_scan_excl(s_b, NB + 1, s_tmp);
-      for (int e = tid; e < cnt; e += RB) {
-        const int u = P.su[off + e], v = P.sv[off + e];
-        const int b = bucket_1d(v + H, G, W2) * G + bucket_1d(u + H, G, W2);
-        const int pos = off + s_b[b] + P.sslot[off + e];
-        P.tu[pos] = u;
-        P.tv[pos] = v;
-        P.tz[pos] = P.sz[off + e];
-        P.trgb[pos] = P.srgb[off + e];
-      }
-      __syncthreads();
-      // ---- b. per-bucket sort + dedupe
-      if (tid == 0) s_k[NB] = 0;
-      for (int b = tid; b < NB; b += RB) {
-        const int lo = off + s_b[b], hi = off + s_b[b + 1];
-        for (int i = lo + 1; i < hi; ++i) {
-          const int u = P.tu[i], v = P.tv[i], zz = P.tz[i];
-          const uint64_t c = P.trgb[i];
-          int j = i - 1;
-          while (j >= lo && pt_less(u, v, zz, c, P.tu[j], P.tv[j], P.tz[j], P.trgb[j])) {
-            P.tu[j + 1] = P.tu[j];
-            P.tv[j + 1] = P.tv[j];
-            P.tz[j + 1] = P.tz[j];
-            P.trgb[j + 1] = P.trgb[j];
-            --j;
-          }
-          P.tu[j + 1] = u;
-          P.tv[j + 1] = v;
-          P.tz[j + 1] = zz;
-          P.trgb[j + 1] = c;
+      // Scatter into bucket order, sort every bucket by (v, u) with the
+      // largest (z, R, G, B) first, drop repeated positions and write the
+      // canonical points.  The sorted copies live in the free middle of the
+      // LDS (between the bucket counts and the kept counts) when the window
+      // fits, else in global memory at the window's offset.
+      auto bucket_sort = [&](int* __restrict__ tu, int* __restrict__ tv, int* __restrict__ tz,
+                             uint64_t* __restrict__ tc, int base) -> int {
+        for (int e = tid; e < cnt; e += RB) {
+          const int u = P.su[off + e], v = P.sv[off + e];
+          const int b = bucket_1d(v + H, G, W2) * G + bucket_1d(u + H, G, W2);
+          const int pos = base + s_b[b] + P.sslot[off + e];
+          tu[pos] = u;
+          tv[pos] = v;
+          tz[pos] = P.sz[off + e];
+          tc[pos] = P.srgb[off + e];
         }
-        int kept = 0;
-        for (int i = lo; i < hi; ++i)
-          if (i == lo || P.tu[i] != P.tu[i - 1] || P.tv[i] != P.tv[i - 1]) ++kept;
-        s_k[b] = kept;
-      }
-      __syncthreads();
-      const int m = __builtin_amdgcn_readfirstlane(block_scan_excl(s_k, NB + 1, s_tmp));
-      for (int b = tid; b < NB; b += RB) {
-        const int lo = off + s_b[b], hi = off + s_b[b + 1];
-        int w = off + s_k[b];
-        for (int i = lo; i < hi; ++i)
-          if (i == lo || P.tu[i] != P.tu[i - 1] || P.tv[i] != P.tv[i - 1]) {
-            P.cuv[w] = make_int2(P.tu[i], P.tv[i]);
-            P.sz[w] = P.tz[i];
-            P.srgb[w] = P.trgb[i];
-            ++w;
+        __syncthreads();
+        // ---- b. per-bucket sort + dedupe
+        if (tid == 0) s_k[NB] = 0;
+        for (int b = tid; b < NB; b += RB) {
+          const int lo = base + s_b[b], hi = base + s_b[b + 1];
+          for (int i = lo + 1; i < hi; ++i) {
+            const int u = tu[i], v = tv[i], zz = tz[i];
+            const uint64_t c = tc[i];
+            int j = i - 1;
+            while (j >= lo && pt_less(u, v, zz, c, tu[j], tv[j], tz[j], tc[j])) {
+              tu[j + 1] = tu[j];
+              tv[j + 1] = tv[j];
+              tz[j + 1] = tz[j];
+              tc[j + 1] = tc[j];
+              --j;
+            }
+            tu[j + 1] = u;
+            tv[j + 1] = v;
+            tz[j + 1] = zz;
+            tc[j + 1] = c;
           }
-      }
-      __syncthreads();
+          int kept = 0;
+          for (int i = lo; i < hi; ++i)
+            if (i == lo || tu[i] != tu[i - 1] || tv[i] != tv[i - 1]) ++kept;
+          s_k[b] = kept;
+        }
+        __syncthreads();
+        const int mm = __builtin_amdgcn_readfirstlane(block_scan_excl(s_k, NB + 1, s_tmp));
+        for (int b = tid; b < NB; b += RB) {
+          const int lo = base + s_b[b], hi = base + s_b[b + 1];
+          int w = off + s_k[b];
+          for (int i = lo; i < hi; ++i)
+            if (i == lo || tu[i] != tu[i - 1] || tv[i] != tv[i - 1]) {
+              P.cuv[w] = make_int2(tu[i], tv[i]);
+              P.sz[w] = tz[i];
+              P.srgb[w] = tc[i];
+              ++w;
+            }
+        }
+        __syncthreads();
+        return mm;
+      };
+      // sorted copies in LDS: colours (8-byte aligned) then u, v, z
+      const int a0 = (NB + 2) & ~1;
+      const bool sort_lds = a0 + 5 * cnt <= LDS_INTS - (NB + 1);
+      int m;
+      if (sort_lds)
+        m = bucket_sort(s_mem + a0 + 2 * cnt, s_mem + a0 + 3 * cnt, s_mem + a0 + 4 * cnt,
+                        reinterpret_cast<uint64_t*>(s_mem + a0), 0);
+      else
+        m = bucket_sort(P.tu, P.tv, P.tz, P.trgb, off);
       int2* s_uv = reinterpret_cast<int2*>(s_mem);
       if (uv_lds)
         for (int p = tid; p < m; p += RB) s_uv[p] = P.cuv[off + p];
