@@ -1074,9 +1074,20 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
                         reinterpret_cast<uint64_t*>(s_mem + a0), 0);
       else
         m = bucket_sort(P.tu, P.tv, P.tz, P.trgb, off);
+      // canonical coordinates in LDS when they fit, and behind them the
+      // colours and heights read per texel by the output pass
       int2* s_uv = reinterpret_cast<int2*>(s_mem);
+      uint64_t* s_c = reinterpret_cast<uint64_t*>(s_mem + 2 * m);
+      int32_t* s_z = s_mem + 4 * m;
+      const bool attr_lds = uv_lds && 5 * m <= LDS_INTS - (NB + 1);
       if (uv_lds)
-        for (int p = tid; p < m; p += RB) s_uv[p] = P.cuv[off + p];
+        for (int p = tid; p < m; p += RB) {
+          s_uv[p] = P.cuv[off + p];
+          if (attr_lds) {
+            s_c[p] = P.srgb[off + p];
+            s_z[p] = P.sz[off + p];
+          }
+        }
       __syncthreads();
       Tile T;
       T.uv = uv_lds ? s_uv : P.cuv + off;
@@ -1085,8 +1096,8 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
       T.H = H;
       T.W2 = W2;
       T.bw = (double)W2 / G;
-      const int32_t* Tz = P.sz + off;
-      const uint64_t* Tc = P.srgb + off;
+      const int32_t* Tz = attr_lds ? s_z : P.sz + off;
+      const uint64_t* Tc = attr_lds ? s_c : P.srgb + off;
       // ---- c. face map reset (the nearest points follow the stars)
       const int q0 = -H + C / 2;
       for (int tt = tid; tt < RR; tt += RB) fm[tt] = FACE_NONE;
