@@ -118,6 +118,25 @@ class Timer:
         return self.a.elapsed_time(self.b) / steps
 
 
+def achievable_peaks(dev):
+    """What this GPU reaches on plain library work, beside the published
+    peaks: a 1 GiB device copy (read + write) and an 8192^3 BF16 GEMM."""
+    timer = Timer()
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    ms_copy = timer.run(lambda: b.copy_(a), 10, 3)
+    del a, b
+    n = 8192
+    g = torch.Generator(device=dev).manual_seed(0)
+    x = torch.randn((n, n), device=dev, generator=g).to(torch.bfloat16).contiguous()
+    y = torch.randn((n, n), device=dev, generator=g).to(torch.bfloat16).contiguous()
+    ms_mm = timer.run(lambda: torch.matmul(x, y), 10, 3)
+    del x, y
+    return {"hbm_copy_GBps": 2 * (1 << 30) / (ms_copy * 1e-3) / 1e9,
+            "bf16_gemm_TFLOPs": 2 * n ** 3 / (ms_mm * 1e-3) / 1e12,
+            "how": "torch copy_ of 1 GiB (bytes read + written); torch.matmul of two 8192x8192 BF16 matrices"}
+
+
 def cpu_baseline(work, sample_idx, gpu_tex_bf16, gpu_tex_fp32, weights64):
     """The FP64 oracle (recon + network forward) on a strided sample of the
     batch, timed on the host cores; also the GPU error on those tiles."""
@@ -317,6 +336,16 @@ def main():
                                   "configs": "0 direct (4 pixel tiles/wave), 1 LDS 16x16 tile, 2 direct (2 pixel tiles/wave), 3 LDS tile, persistent with patch prefetch"},
         "tile_status_nonzero": int((status != 0).sum()),
     }
+    try:
+        peaks = achievable_peaks(dev)
+        out["achievable_peaks"] = peaks
+        if roof["unit"] == "GB/s":
+            roof["frac_of_achievable"] = roof["achieved"] / peaks["hbm_copy_GBps"]
+        if roof_conv["achieved"]:
+            roof_conv["frac_of_achievable"] = roof_conv["achieved"] / peaks["bf16_gemm_TFLOPs"]
+            roof_conv["hbm_frac_of_achievable"] = roof_conv["hbm_algorithmic_GBps"] / peaks["hbm_copy_GBps"]
+    except Exception as e:  # secondary figure only
+        out["achievable_peaks"] = {"error": repr(e)}
 
     # ---------------------------------------------------------------- secondary figures
     if not args.no_secondary:
