@@ -328,6 +328,7 @@ def main():
                    "tiles": nt, "sparse_points": ps.n, "res": res, "pad": g.pad, "grid": f"{R}x{R}x8"},
         "roofline": roof,
         "roofline_conv": roof_conv,
+        "sparse_points_per_s": ps.n / (ms16 * 1e-3),
         "fp32_plain": {"tiles_per_s": nt / (ms32 * 1e-3), "ms_per_step": ms32},
         "bf16_vs_fp32": ms32 / ms16,
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kernels.items())},
