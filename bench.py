@@ -229,11 +229,13 @@ def main():
     log(f"workload: {nt} tiles, {ps.n} sparse points")
 
     def step_bf16():
-        ls.recon_tiles(g, x, y, z, rgb, tl, x_out=x_out, cz_out=cz, status=st, ws=ws_recon)
+        ls.recon_tiles(g, x, y, z, rgb, tl, order=ls.ORDER_LONGEST_FIRST, x_out=x_out, cz_out=cz, status=st,
+                       ws=ws_recon)
         ls.refine_tiles(w, x_out, cz, g, ls.BF16, w_bf16=wb, tex_out=tex16, want_y=False, ws=ws16)
 
     def step_fp32():
-        ls.recon_tiles(g, x, y, z, rgb, tl, x_out=x_out, cz_out=cz, status=st, ws=ws_recon)
+        ls.recon_tiles(g, x, y, z, rgb, tl, order=ls.ORDER_LONGEST_FIRST, x_out=x_out, cz_out=cz, status=st,
+                       ws=ws_recon)
         ls.refine_tiles(w, x_out, cz, g, ls.FP32, tex_out=tex32, want_y=False, ws=ws32)
 
     # ---------------------------------------------------------------- conv tilings

@@ -58,7 +58,8 @@ typedef enum ls_status {
   LS_EHIP = -3,       /* HIP runtime error (see ls_last_error) */
   LS_ENOTIMPL = -4,   /* option not implemented */
   LS_EWORKSPACE = -5, /* workspace smaller than ls_workspace_bytes() */
-  LS_ECAP = -6        /* a caller-sized output cannot hold the result */
+  LS_ECAP = -6,       /* a caller-sized output cannot hold the result */
+  LS_ESCRATCH = -7    /* input larger than a fixed-size scratch entry point accepts */
 } ls_status;
 
 /* per-tile status flags written by ls_recon_tiles */
@@ -71,6 +72,16 @@ typedef enum ls_tile_flag {
 } ls_tile_flag;
 
 typedef enum ls_precision { LS_FP32 = 0, LS_BF16 = 1 } ls_precision;
+
+/* Order in which ls_recon_tiles takes its tiles from the work queue.
+ *  LS_ORDER_LIST: the order of tile_list, e.g. by distance to the viewer, so
+ *    that construction is prioritised towards the viewpoint (Section 1 and
+ *    the Section 4.1 discussion of Table 2: nearby heightmaps first).
+ *  LS_ORDER_LONGEST_FIRST: descending window point count (in steps of 4
+ *    points), so the last tiles to start are short and the workgroups finish
+ *    together; for throughput on a batch with no priority.
+ * Results per output slot do not depend on the order. */
+typedef enum ls_order { LS_ORDER_LIST = 0, LS_ORDER_LONGEST_FIRST = 1 } ls_order;
 
 typedef enum ls_op { LS_OP_RECON = 0, LS_OP_REFINE = 1, LS_OP_BACKWARD = 2, LS_OP_SPLAT = 3 } ls_op;
 
@@ -92,10 +103,11 @@ size_t ls_act_bytes(const ls_grid* g, int32_t n_tiles, int precision);
 
 /* Tile binning + Algorithm 1 + normalisation (Sections 3.3-3.4).
  *  x, y, z [n] int32 raw; rgb [n][3] uint16 (16-bit LAS colour).
- *  tile_list [n_tiles]: linear tile ids ty*tiles_x + tx, distinct, in the
- *    order tiles are to be processed (e.g. by distance to the viewer,
- *    which the paper uses to prioritise construction).  Output slot k
- *    belongs to tile_list[k].
+ *  tile_list [n_tiles]: linear tile ids ty*tiles_x + tx, distinct.  Output
+ *    slot k belongs to tile_list[k].
+ *  order: ls_order; LS_ORDER_LIST processes the tiles in tile_list order
+ *    (workgroups take them from a queue in that order), LS_ORDER_LONGEST_FIRST
+ *    by descending window point count.  Other values: LS_ERANGE.
  *  x_out [n_tiles][R][R][8] FP32: channel 0 (h_lin - cz)/r, 1 (h_nn - cz)/r,
  *    2-4 linear RGB/65535, 5-7 nearest RGB/65535, with r = H*scale_xy
  *    metres and h in metres.
@@ -110,7 +122,7 @@ size_t ls_act_bytes(const ls_grid* g, int32_t n_tiles, int precision);
  * go to the smallest (d^2, y, x); duplicate positions keep the largest
  * (z, R, G, B).  Linear values cover exactly the closed convex hull. */
 int ls_recon_tiles(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
-                   int64_t n, const int32_t* tile_list, int32_t n_tiles, float* x_out, double* cz_out,
+                   int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order, float* x_out, double* cz_out,
                    int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
                    size_t ws_bytes, void* stream);
 
@@ -130,11 +142,17 @@ int ls_refine_tiles(const float* w, const uint16_t* w_bf16, int precision, const
                     int32_t n_tiles, const ls_grid* g, float* y_out, float* tex_out, void* act_save, void* ws,
                     size_t ws_bytes, void* stream);
 
-/* Refinement network backward: given dL/dy [n_tiles][res][res][4] for the
- * normalised output, writes grad_w [num_params] (overwritten, summed over
- * the batch) and, if non-null, grad_x [n_tiles][R][R][8].  act_save: the
- * buffer filled by ls_refine_tiles with the same inputs and precision, or
- * NULL to recompute the forward inside (activation recomputation).
+/* Refinement network backward, for training the network (Section 3.4,
+ * training paragraph: the network is fitted to ground-truth heightmaps with a
+ * loss on its normalised output; any loss can be used, the caller supplies
+ * its gradient).  Given dL/dy [n_tiles][res][res][4] for the normalised
+ * output, writes grad_w [num_params] (overwritten, summed over the batch) and,
+ * if non-null, grad_x [n_tiles][R][R][8].  act_save: the buffer filled by
+ * ls_refine_tiles with the same inputs and precision, or NULL to recompute
+ * the forward inside (activation recomputation).
+ * Errors: LS_EINVAL for a null grad_w or (n_tiles > 0) null w, x or grad_y,
+ * or a null w_bf16 with LS_BF16; LS_ERANGE for another precision;
+ * LS_EWORKSPACE for a short workspace.
  *  ws: ls_workspace_bytes(LS_OP_BACKWARD, g, n_tiles, 0, precision). */
 int ls_refine_backward(const float* w, const uint16_t* w_bf16, int precision, const float* x,
                        const void* act_save, const float* grad_y, int32_t n_tiles, const ls_grid* g, float* grad_w,

@@ -20,10 +20,11 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblidarscout.so")
 
-LS_OK, LS_EINVAL, LS_ERANGE, LS_EHIP, LS_ENOTIMPL, LS_EWORKSPACE, LS_ECAP = 0, -1, -2, -3, -4, -5, -6
+LS_OK, LS_EINVAL, LS_ERANGE, LS_EHIP, LS_ENOTIMPL, LS_EWORKSPACE, LS_ECAP, LS_ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
 TILE_EMPTY, TILE_NN_ONLY, TILE_CAP, TILE_DEGENERATE, TILE_BADID = 1, 2, 4, 8, 16
 FP32, BF16 = 0, 1
 OP_RECON, OP_REFINE, OP_BACKWARD, OP_SPLAT = 0, 1, 2, 3
+ORDER_LIST, ORDER_LONGEST_FIRST = 0, 1
 
 EXPORTS = [
     "ls_num_params", "ls_workspace_bytes", "ls_act_bytes", "ls_recon_tiles", "ls_refine_tiles",
@@ -93,7 +94,7 @@ def load_library(path: str = LIB_PATH):
         lib.ls_act_bytes.restype = sz
         lib.ls_act_bytes.argtypes = [G, i32, ctypes.c_int]
         lib.ls_recon_tiles.restype = ctypes.c_int
-        lib.ls_recon_tiles.argtypes = [G, P, P, P, P, i64, P, i32, P, P, P, P, i64, P, P, sz, P]
+        lib.ls_recon_tiles.argtypes = [G, P, P, P, P, i64, P, i32, i32, P, P, P, P, i64, P, P, sz, P]
         lib.ls_refine_tiles.restype = ctypes.c_int
         lib.ls_refine_tiles.argtypes = [P, P, ctypes.c_int, P, P, i32, G, P, P, P, P, sz, P]
         lib.ls_refine_backward.restype = ctypes.c_int
@@ -181,9 +182,12 @@ def alloc_workspace(nbytes: int, device=None) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device or "cuda")
 
 
-def recon_tiles(grid, x, y, z, rgb, tile_list, *, x_out=None, cz_out=None, bin_off=None, bin_idx=None,
-                bin_cap: int = 0, status=None, ws=None, stream=None):
-    """Binning + Algorithm 1 + normalisation -> (x_out [n,R,R,8] f32, cz [n] f64, status [n] i32)."""
+def recon_tiles(grid, x, y, z, rgb, tile_list, *, order: int = ORDER_LIST, x_out=None, cz_out=None, bin_off=None,
+                bin_idx=None, bin_cap: int = 0, status=None, ws=None, stream=None):
+    """Binning + Algorithm 1 + normalisation -> (x_out [n,R,R,8] f32, cz [n] f64, status [n] i32).
+
+    order: ORDER_LIST processes the tiles in tile_list order (viewpoint
+    priority), ORDER_LONGEST_FIRST by descending window point count."""
     lib = load_library()
     g = Grid.of(grid)
     n = x.numel()
@@ -215,7 +219,7 @@ def recon_tiles(grid, x, y, z, rgb, tile_list, *, x_out=None, cz_out=None, bin_o
     _need(ws, "ws", (torch.uint8,), numel=need)
     gc = g.c()
     rc = lib.ls_recon_tiles(ctypes.byref(gc), _ptr(x), _ptr(y), _ptr(z), _ptr(rgb), n, _ptr(tile_list), nt,
-                            _ptr(x_out), _ptr(cz_out), _ptr(bin_off), _ptr(bin_idx), int(bin_cap), _ptr(status),
+                            int(order), _ptr(x_out), _ptr(cz_out), _ptr(bin_off), _ptr(bin_idx), int(bin_cap), _ptr(status),
                             _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "ls_recon_tiles")
     return x_out, cz_out, status

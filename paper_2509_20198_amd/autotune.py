@@ -7,18 +7,22 @@ gradient).  All tilings of a (layer, precision, pass) compute the same
 result; they differ only in speed for a given shape.  The tuner times the
 whole forward (pass 0) or forward + backward (passes 1, 2) on the real batch
 shape with HIP events, changing one layer at a time (coordinate descent,
-median of `reps` runs), keeps the fastest tiling per layer, applies it, and
-caches the choice in a JSON file keyed by device name, grid shape, batch
-size, precision and passes.
+median of `reps` runs; the library's default, -1, is one of the
+candidates), keeps the fastest tiling per layer and applies it.  If the
+tuned set is not faster than the defaults on a final timing, the defaults
+are kept.  The choice is cached in a JSON file keyed by device name, grid
+shape, batch size, precision, passes and a hash of the built library, so a
+rebuilt library is tuned again.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 
 import torch
 
-from . import (BF16, FP32, OP_BACKWARD, OP_REFINE, Grid, act_bytes, alloc_workspace, conv_num_configs,
+from . import (BF16, FP32, LIB_PATH, OP_BACKWARD, OP_REFINE, Grid, act_bytes, alloc_workspace, conv_num_configs,
                get_conv_config, num_params, pack_weights_bf16, refine_backward, refine_tiles, set_conv_config,
                workspace_bytes)
 
@@ -30,9 +34,22 @@ def default_cache_path() -> str:
                           os.path.join(os.path.expanduser("~"), ".cache", "lidarscout_mi355x", "autotune.json"))
 
 
+_lib_hash = None
+
+
+def library_hash() -> str:
+    """First 16 hex digits of the SHA-256 of the built library."""
+    global _lib_hash
+    if _lib_hash is None:
+        with open(LIB_PATH, "rb") as f:
+            _lib_hash = hashlib.sha256(f.read()).hexdigest()[:16]
+    return _lib_hash
+
+
 def _key(g: Grid, n_tiles: int, precision: int, passes) -> str:
     name = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
-    return f"{name}|R{g.R}|res{g.res}|n{n_tiles}|{'bf16' if precision == BF16 else 'fp32'}|passes{''.join(map(str, passes))}"
+    return (f"{name}|lib{library_hash()}|R{g.R}|res{g.res}|n{n_tiles}|{'bf16' if precision == BF16 else 'fp32'}"
+            f"|passes{''.join(map(str, passes))}")
 
 
 def _median_ms(fn, reps: int) -> float:
@@ -108,8 +125,8 @@ def autotune(grid, n_tiles: int, precision: int = BF16, passes=(0,), reps: int =
             n = conv_num_configs(layer, precision, p)
             if n <= 1:
                 continue
-            best_c, best_t = get_conv_config(layer, precision, p), None
-            for c in range(n):
+            best_c, best_t = -1, None
+            for c in range(-1, n):
                 set_conv_config(layer, precision, p, c)
                 t = _median_ms(run, reps)
                 if best_t is None or t < best_t:
@@ -117,7 +134,13 @@ def autotune(grid, n_tiles: int, precision: int = BF16, passes=(0,), reps: int =
             set_conv_config(layer, precision, p, best_c)
             choice[f"{layer},{p}"] = best_c
     ms_tuned = _median_ms(run, reps)
-    out = {"key": key, "choice": choice, "ms_default": ms_default, "ms_tuned": ms_tuned}
+    kept_default = ms_tuned >= ms_default
+    if kept_default:
+        reset(precision, passes)
+        choice = {k: -1 for k in choice}
+        ms_tuned = ms_default
+    out = {"key": key, "choice": choice, "ms_default": ms_default, "ms_tuned": ms_tuned,
+           "kept_default": kept_default}
     cache[key] = out
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)

@@ -52,6 +52,8 @@ void ls_set_last_error(hipError_t e, const char* what, int line) {
   snprintf(g_last_error, sizeof(g_last_error), "%s (%d) at %s, line %d", hipGetErrorString(e), (int)e, what, line);
 }
 
+void ls_set_last_message(const char* what) { snprintf(g_last_error, sizeof(g_last_error), "%s", what); }
+
 int ls_zero_f32(float* p, int64_t n, hipStream_t st) {
   if (n <= 0) return LS_OK;
   const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
@@ -103,6 +105,7 @@ const char* ls_status_string(int status) {
     case LS_ENOTIMPL: return "not implemented";
     case LS_EWORKSPACE: return "workspace smaller than ls_workspace_bytes()";
     case LS_ECAP: return "output capacity too small";
+    case LS_ESCRATCH: return "input larger than the fixed scratch of this entry point";
     default: return "unknown status";
   }
 }
@@ -125,19 +128,20 @@ size_t ls_act_bytes(const ls_grid* g, int32_t n_tiles, int precision) {
 }
 
 int ls_recon_tiles(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
-                   int64_t n, const int32_t* tile_list, int32_t n_tiles, float* x_out, double* cz_out,
+                   int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order, float* x_out, double* cz_out,
                    int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
                    size_t ws_bytes, void* stream) {
   LsGridInfo gi;
   const int rc = ls_grid_info(g, &gi);
   if (rc != LS_OK) return rc;
+  if (order != LS_ORDER_LIST && order != LS_ORDER_LONGEST_FIRST) return LS_ERANGE;
   if (n < 0 || n_tiles < 0 || n > 0x7fffffffLL) return LS_EINVAL;
   if (n > 0 && (!x || !y || !z || !rgb)) return LS_EINVAL;
   if (n_tiles > 0 && (!tile_list || !x_out || !cz_out || !tile_status)) return LS_EINVAL;
   if ((bin_off == nullptr) != (bin_idx == nullptr)) return LS_EINVAL;
   if (bin_idx && bin_cap < 0) return LS_EINVAL;
   if ((int64_t)gi.tx * gi.ty > 0x7fffffffLL) return LS_ERANGE;
-  return ls_recon_impl(gi, x, y, z, rgb, n, tile_list, n_tiles, x_out, cz_out, bin_off, bin_idx, bin_cap,
+  return ls_recon_impl(gi, x, y, z, rgb, n, tile_list, n_tiles, order, x_out, cz_out, bin_off, bin_idx, bin_cap,
                        tile_status, ws, ws_bytes, ls_stream(stream));
 }
 

@@ -25,6 +25,7 @@
   } while (0)
 
 void ls_set_last_error(hipError_t e, const char* what, int line);
+void ls_set_last_message(const char* what);
 
 // Optional launch timing: when enabled with ls_trace_enable(), a scope
 // records a start event on `st` at construction and a stop event at the end
@@ -123,7 +124,7 @@ size_t ls_refine_ws_bytes(const LsGridInfo& gi, int32_t n_tiles, int precision, 
 size_t ls_refine_act_bytes(const LsGridInfo& gi, int32_t n_tiles, int precision);
 size_t ls_recon_ws_bytes(const LsGridInfo& gi, int32_t n_tiles, int64_t n);
 int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
-                  int64_t n, const int32_t* tile_list, int32_t n_tiles, float* x_out, double* cz_out,
+                  int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order, float* x_out, double* cz_out,
                   int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
                   size_t ws_bytes, hipStream_t st);
 int ls_splat_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,

@@ -8,9 +8,10 @@
 //      4 windows with the paper's 16-texel ring).
 //   3. k_bin_sort (only when the caller asks for the CSR): ascending order.
 //   4. k_recon: persistent, one workgroup per tile popped from a queue that
-//      holds the tiles by descending window point count (longest first, so
-//      the last tiles to start are short and the workgroups finish
-//      together).  Phases, separated by barriers:
+//      holds the tiles in the caller's list order (viewpoint priority) or by
+//      descending window point count (longest first, so the last tiles to
+//      start are short and the workgroups finish together).  Phases,
+//      separated by barriers:
 //        a. gather the tile's points to tile-local coordinates and bucket
 //           them into a G x G grid over the window (LDS counting sort);
 //        b. sort each bucket by (v, u) and drop duplicate positions,
@@ -65,6 +66,7 @@ struct BinParams {
   int64_t cap;
   int32_t* flags;  // [0]: cap overflow
   int32_t* order;  // recon processing order (tile slots)
+  int32_t order_mode;  // LS_ORDER_LIST or LS_ORDER_LONGEST_FIRST
 };
 
 // floor(a / S) for |a| < 2^53: the double quotient is within one of it
@@ -184,9 +186,9 @@ __device__ __forceinline__ int order_key(int32_t count) {
 }
 
 // Single-workgroup exclusive scan of counts -> bin_off (n_tiles + 1 entries),
-// then the recon processing order: a counting sort of the tile slots by
-// order_key (slots with equal keys in any order; the results do not depend
-// on the order).
+// then the recon processing order: the caller's list order, or a counting
+// sort of the tile slots by order_key (slots with equal keys in any order;
+// the results do not depend on the order).
 __global__ void __launch_bounds__(1024) k_bin_scan(BinParams p) {
   __shared__ int64_t s_part[1024];
   __shared__ int64_t s_carry;
@@ -215,6 +217,10 @@ __global__ void __launch_bounds__(1024) k_bin_scan(BinParams p) {
     const int64_t total = s_carry;
     p.bin_off[p.n_tiles] = (int32_t)(total < 0x7fffffff ? total : 0x7fffffff);
     p.flags[0] = total > p.cap ? 1 : 0;
+  }
+  if (p.order_mode == LS_ORDER_LIST) {
+    for (int i = tid; i < p.n_tiles; i += 1024) p.order[i] = i;
+    return;
   }
   constexpr int PER = ORDER_KEYS / 1024;
   for (int b = tid; b < ORDER_KEYS; b += 1024) s_hist[b] = 0;
@@ -251,10 +257,10 @@ __global__ void k_bin_scatter(BinParams p) {
 }
 
 // In-place ascending bitonic sort of one bin segment; segments longer than
-// SORT_LDS use `scratch` (2 entries per bin entry, so the power-of-two
+// SORT_LDS use `spill` (2 entries per bin entry, so the power-of-two
 // padding always fits).
 __global__ void __launch_bounds__(RB) k_bin_sort(const int32_t* __restrict__ bin_off, int32_t n_tiles,
-                                                 int32_t* __restrict__ bin_idx, int32_t* __restrict__ scratch,
+                                                 int32_t* __restrict__ bin_idx, int32_t* __restrict__ spill,
                                                  const int32_t* __restrict__ flags) {
   __shared__ int32_t s_buf[SORT_LDS];
   if (flags[0]) return;
@@ -264,7 +270,7 @@ __global__ void __launch_bounds__(RB) k_bin_sort(const int32_t* __restrict__ bin
     if (cnt <= 1) continue;  // uniform: k comes from blockIdx, the counts are readfirstlane'd
     int n2 = 1;
     while (n2 < cnt) n2 <<= 1;
-    int32_t* buf = n2 <= SORT_LDS ? s_buf : scratch + 2 * (int64_t)off;
+    int32_t* buf = n2 <= SORT_LDS ? s_buf : spill + 2 * (int64_t)off;
     for (int i = threadIdx.x; i < n2; i += RB) buf[i] = i < cnt ? bin_idx[off + i] : 0x7fffffff;
     __syncthreads();
     for (int kk = 2; kk <= n2; kk <<= 1)
@@ -1370,11 +1376,11 @@ int recon_wg_count(int32_t n_tiles) {
   return n_tiles < want ? (n_tiles > 0 ? n_tiles : 1) : want;
 }
 
-size_t recon_layout(const LsGridInfo& gi, int32_t n_tiles, int64_t n, void* base, ReconLayout* L) {
+// Workspace layout for n_tiles tiles, n points and nwg recon workgroups.
+size_t recon_layout(const LsGridInfo& gi, int32_t n_tiles, int64_t n, void* base, ReconLayout* L, int nwg) {
   LsArena A{reinterpret_cast<char*>(base), 0, 0};
   const int64_t nall = (int64_t)gi.tx * gi.ty;
   const int64_t E = n * max_multiplicity(gi) + 1;
-  const int nwg = recon_wg_count(n_tiles);
   const int64_t RR = (int64_t)gi.R * gi.R;
   L->tile_pos = A.take<int32_t>(nall);
   L->counts = A.take<int32_t>(n_tiles + 1);
@@ -1405,22 +1411,14 @@ size_t recon_layout(const LsGridInfo& gi, int32_t n_tiles, int64_t n, void* base
   return A.used;
 }
 
-}  // namespace
-
-size_t ls_recon_ws_bytes(const LsGridInfo& gi, int32_t n_tiles, int64_t n) {
+// Enqueue the whole recon pipeline with its workspace at `ws` laid out for
+// nwg recon workgroups (the caller has checked that it is large enough).
+int recon_enqueue(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                  int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order, float* x_out, double* cz_out,
+                  int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws, int nwg,
+                  hipStream_t st) {
   ReconLayout L;
-  return recon_layout(gi, n_tiles, n, nullptr, &L);
-}
-
-int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
-                  int64_t n, const int32_t* tile_list, int32_t n_tiles, float* x_out, double* cz_out,
-                  int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
-                  size_t ws_bytes, hipStream_t st) {
-  if (n_tiles <= 0) return LS_OK;
-  ReconLayout L;
-  const size_t need = recon_layout(gi, n_tiles, n, nullptr, &L);
-  if (ws_bytes < need || !ws) return LS_EWORKSPACE;
-  recon_layout(gi, n_tiles, n, ws, &L);
+  recon_layout(gi, n_tiles, n, ws, &L, nwg);
   const bool user_csr = bin_off && bin_idx;
   int32_t* boff = user_csr ? bin_off : L.bin_off;
   int32_t* bidx = user_csr ? bin_idx : L.bin_idx;
@@ -1463,6 +1461,7 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   bp.cap = cap;
   bp.flags = L.flags;
   bp.order = L.order;
+  bp.order_mode = order;
   const int pb = (int)std::min<int64_t>((n + T - 1) / T, 8192);
   // workgroup-private histograms when the tile list fits in LDS
   const bool lds_bins = n_tiles <= BIN_LDS_TILES;
@@ -1541,4 +1540,24 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
   }
   LS_LAUNCH_CHECK();
   return LS_OK;
+}
+
+}  // namespace
+
+size_t ls_recon_ws_bytes(const LsGridInfo& gi, int32_t n_tiles, int64_t n) {
+  ReconLayout L;
+  return recon_layout(gi, n_tiles, n, nullptr, &L, recon_wg_count(n_tiles));
+}
+
+int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                  int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order, float* x_out, double* cz_out,
+                  int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
+                  size_t ws_bytes, hipStream_t st) {
+  if (n_tiles <= 0) return LS_OK;
+  ReconLayout L;
+  const int nwg = recon_wg_count(n_tiles);
+  const size_t need = recon_layout(gi, n_tiles, n, nullptr, &L, nwg);
+  if (ws_bytes < need || !ws) return LS_EWORKSPACE;
+  return recon_enqueue(gi, x, y, z, rgb, n, tile_list, n_tiles, order, x_out, cz_out, bin_off, bin_idx, bin_cap,
+                       tile_status, ws, nwg, st);
 }

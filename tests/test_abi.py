@@ -57,13 +57,17 @@ def test_grid_validation(lib):
         assert ls.workspace_bytes(ls.OP_RECON, g, 1, 1) == 0
     # entry points reject invalid arguments on the host, before touching the GPU
     gc = ls.Grid(res=63).c()
-    rc = lib.ls_recon_tiles(ctypes.byref(gc), None, None, None, None, 0, None, 0, None, None, None, None, 0, None,
-                            None, 0, None)
+    rc = lib.ls_recon_tiles(ctypes.byref(gc), None, None, None, None, 0, None, 0, 0, None, None, None, None, 0,
+                            None, None, 0, None)
     assert rc == ls.LS_ERANGE
     gc = ls.Grid().c()
-    rc = lib.ls_recon_tiles(ctypes.byref(gc), None, None, None, None, 10, None, 1, None, None, None, None, 0, None,
-                            None, 0, None)
+    rc = lib.ls_recon_tiles(ctypes.byref(gc), None, None, None, None, 10, None, 1, 0, None, None, None, None, 0,
+                            None, None, 0, None)
     assert rc == ls.LS_EINVAL
+    # an unknown processing order
+    rc = lib.ls_recon_tiles(ctypes.byref(gc), None, None, None, None, 0, None, 0, 2, None, None, None, None, 0,
+                            None, None, 0, None)
+    assert rc == ls.LS_ERANGE
     rc = lib.ls_refine_tiles(None, None, 7, None, None, 1, ctypes.byref(gc), None, None, None, None, 0, None)
     assert rc == ls.LS_ERANGE
     rc = lib.ls_splat_points(ctypes.byref(gc), None, None, None, None, 5, None, 1, None, None, None, None)

@@ -68,9 +68,15 @@ def test_autotune_applies_and_caches(tmp_path):
     assert not r["cached"] and r["ms_tuned"] > 0
     for k, c in r["choice"].items():
         layer, p = (int(v) for v in k.split(","))
-        assert 0 <= c < ls.conv_num_configs(layer, ls.BF16, p)
+        assert -1 <= c < ls.conv_num_configs(layer, ls.BF16, p)
         assert ls.get_conv_config(layer, ls.BF16, p) == c
+    # the defaults are kept unless the tuned set is faster
+    if r["kept_default"]:
+        assert r["ms_tuned"] == r["ms_default"] and all(c == -1 for c in r["choice"].values())
+    else:
+        assert r["ms_tuned"] < r["ms_default"]
     assert r["key"] in json.load(open(path))
+    assert AT.library_hash() in r["key"]
     AT.reset(ls.BF16)
     r2 = AT.autotune(g, 16, ls.BF16, passes=(0, 1, 2), cache_path=path)
     assert r2["cached"] and r2["choice"] == r["choice"]
