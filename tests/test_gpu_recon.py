@@ -247,3 +247,30 @@ def test_viewpoint_priority_order():
     assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["cz"], b["cz"])
     assert np.array_equal(a["status"], b["status"]) and np.array_equal(a["idx"], b["idx"])
     _compare(w.region, ps, w.tile_list, gpu=a)
+
+
+def test_cocircular_lattice_with_relief():
+    """Lattice points with random heights: many exactly cocircular squares
+    whose two diagonals give different heights, texel centres on the
+    diagonals.  The GPU's symbolic perturbation picks one triangulation; its
+    linear map must come from a valid Delaunay triangulation at every texel
+    (several are correct), and its nearest-neighbour map (unique) must equal
+    the oracle's."""
+    from delaunay_check import check_linear_valid, lattice_points
+
+    region = synth.Region()
+    rng = np.random.default_rng(31)
+    u, v, z = lattice_points(rng)
+    ps = ((u + 32000).astype(np.int32), (v + 32000).astype(np.int32), z.astype(np.int32),
+          np.zeros((len(u), 3), np.uint16))
+    gpu = _gpu_recon(region, ps, np.zeros(1, np.int32), want_csr=False)
+    xo, cz, st = oracle.recon_tiles(region, *ps, np.zeros(1, np.int32))
+    assert np.abs(gpu["x"][0, ..., 1] - xo[0, ..., 1]).max() * R_M <= 1e-5
+    H = 48000
+    c = -H + 500 + 1000 * np.arange(96)
+    qx, qy = np.meshgrid(c, c)
+    h_lin = gpu["x"][0, ..., 0] * R_M + gpu["cz"][0]
+    h_nn = gpu["x"][0, ..., 1] * R_M + gpu["cz"][0]
+    n, amb = check_linear_valid(np.stack([u, v], 1), z * 0.01, qx, qy, h_lin, h_nn, TOL_M)
+    print(f"lattice: {amb} of {n} texels had two admissible values")
+    assert amb > 100

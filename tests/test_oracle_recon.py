@@ -338,3 +338,123 @@ def test_golden_three_point_tile(oracle_lib):
             assert abs(out["hm_lin"][i, j] - float(r[3])) < 1e-12
             assert abs(out["hm_nn"][i, j] - float(r[4])) < 1e-12
             assert bool(out["inside"][i, j]) == (r[5] == "inside")
+
+
+def test_golden_three_point_texture(oracle_lib):
+    """Texture of the three-point tile through the all-zero network, and the
+    colour clamp, against hand-derived values (golden/three_point_texture.txt):
+    pins oracle.texture (h = c_z + r y_h, colour clamp) and the network's
+    residual on the crop."""
+    rows = _load_golden("three_point_tile.txt")
+    pts = [r[1:] for r in rows if r[0] == "point"]
+    region = synth.Region()
+    out = oracle_lib.recon_tile(region, oracle_lib.make_points(
+        [int(p[0]) for p in pts], [int(p[1]) for p in pts], [int(p[2]) for p in pts],
+        [[int(c) for c in p[3:6]] for p in pts]))
+    w0 = np.zeros(oracle_lib.num_params())
+    y = oracle_lib.unet_forward(w0, out["x"][None], region.res, region.pad)
+    tex = oracle_lib.texture(y, np.array([out["cz"]]), region)[0]
+    gold = _load_golden("three_point_texture.txt")
+    n = 0
+    for r in gold:
+        if r[0] == "ctexel":
+            i, j = int(r[1]), int(r[2])
+            want = [float(v) for v in r[3:7]]
+            np.testing.assert_allclose(tex[i, j], want, rtol=0, atol=1e-12)
+            n += 1
+        elif r[0] == "clamp":
+            yv = np.array([float(v) for v in r[1:5]]).reshape(1, 1, 1, 4)
+            got = oracle_lib.texture(yv, np.array([20.25]), region)[0, 0, 0]
+            np.testing.assert_allclose(got, [float(v) for v in r[5:9]], rtol=0, atol=1e-12)
+            n += 1
+    assert n == 8
+
+
+def test_recon_tiles_equals_per_tile_composition(oracle_lib):
+    """The batch driver = binning, gather to tile-local coordinates and
+    Algorithm 1 per listed tile, on a region with tiles_x != tiles_y, a
+    non-zero origin and a tile list out of id order.  Tile centres come from
+    the tiling's definition (tile (tx, ty) covers [origin + t S, origin +
+    (t + 1) S) per axis, linear id ty * tiles_x + tx), enumerated row by row."""
+    rng = np.random.default_rng(21)
+    region = synth.Region(origin_x=-12345, origin_y=777, tiles_x=3, tiles_y=2)
+    S = region.tile_size
+    H = S // 2 + region.pad * region.cell
+    n = 1500
+    x = rng.integers(region.origin_x - 20000, region.origin_x + 3 * S + 20000, n)
+    y = rng.integers(region.origin_y - 20000, region.origin_y + 2 * S + 20000, n)
+    z = rng.integers(-3000, 3000, n)
+    rgb = rng.integers(0, 65536, (n, 3))
+    tile_list = np.array([5, 0, 3, 1], np.int32)
+    xo, cz, st = oracle_lib.recon_tiles(region, x, y, z, rgb, tile_list)
+    centres = []
+    for ty in range(region.tiles_y):
+        for tx in range(region.tiles_x):
+            lo_x, lo_y = region.origin_x + tx * S, region.origin_y + ty * S
+            centres.append((lo_x + S // 2, lo_y + S // 2))
+    for k, t in enumerate(tile_list):
+        cx, cy = centres[t]
+        sel = [i for i in range(n) if cx - H <= x[i] < cx + H and cy - H <= y[i] < cy + H]
+        ref = oracle_lib.recon_tile(region, oracle_lib.make_points(x[sel] - cx, y[sel] - cy, z[sel], rgb[sel]))
+        np.testing.assert_allclose(xo[k], ref["x"], rtol=0, atol=1e-12)
+        assert abs(cz[k] - ref["cz"]) <= 1e-12 and st[k] == ref["status"]
+
+
+def test_recon_tiles_plane_in_region_coordinates(oracle_lib):
+    """A plane in region coordinates, z = (3x - 2y)/100 + 500 raw, sampled on
+    the 100 cm lattice (plus every window's corner lattice points, so each
+    hull covers all texel centres), is reproduced by the batch driver at every
+    texel of every listed tile at the texel centre's region coordinates:
+    pins the tile centres and axes of the batch driver by a closed form."""
+    rng = np.random.default_rng(22)
+    region = synth.Region(origin_x=-12300, origin_y=700, tiles_x=3, tiles_y=2)
+    S = region.tile_size
+    H = S // 2 + region.pad * region.cell
+    x0, y0 = region.origin_x - H, region.origin_y - H
+    nx, ny = (3 * S + 2 * H) // 100, (2 * S + 2 * H) // 100
+    g = rng.choice(nx * ny, 40000, replace=False)
+    x = x0 + (g % nx) * 100
+    y = y0 + (g // nx) * 100
+    tile_list = np.array([4, 2, 0], np.int32)
+    cx_all, cy_all = [], []
+    for t in tile_list:
+        cx = region.origin_x + (t % 3) * S + S // 2
+        cy = region.origin_y + (t // 3) * S + S // 2
+        lo_x, hi_x = cx - H, cx + H - 100  # lattice points: region origin offsets are multiples of 100
+        lo_y, hi_y = cy - H, cy + H - 100
+        cx_all += [lo_x, hi_x, lo_x, hi_x]
+        cy_all += [lo_y, lo_y, hi_y, hi_y]
+    x = np.concatenate([x, cx_all])
+    y = np.concatenate([y, cy_all])
+    assert np.all((x - x0) % 100 == 0) and np.all((y - y0) % 100 == 0)
+    z = (3 * x - 2 * y) // 100 + 500
+    assert np.all((3 * x - 2 * y) % 100 == 0)
+    xo, cz, st = oracle_lib.recon_tiles(region, x, y, z, np.zeros((len(x), 3), int), tile_list)
+    c = -H + region.cell // 2 + region.cell * np.arange(region.R)
+    for k, t in enumerate(tile_list):
+        cx = region.origin_x + (t % 3) * S + S // 2
+        cy = region.origin_y + (t // 3) * S + S // 2
+        qx, qy = np.meshgrid(cx + c, cy + c)
+        plane = ((3 * qx - 2 * qy) / 100 + 500) * 0.01
+        h = xo[k, ..., 0] * 480.0 + cz[k]
+        np.testing.assert_allclose(h, plane, rtol=0, atol=1e-9)
+        assert st[k] == 0
+
+
+def test_cocircular_lattice_interpolation_valid(oracle_lib):
+    """Lattice points with random heights (exactly cocircular squares, whose
+    two diagonals give different heights; texels sit on the diagonals): the
+    oracle's linear map comes from a valid Delaunay triangulation at every
+    texel, and the test is not vacuous (many texels have two admissible
+    values)."""
+    from delaunay_check import check_linear_valid, lattice_points
+
+    region = synth.Region()
+    rng = np.random.default_rng(31)
+    u, v, z = lattice_points(rng)
+    out = oracle_lib.recon_tile(region, oracle_lib.make_points(u, v, z, np.zeros((len(u), 3), int)))
+    cp = out["points"]
+    qx, qy = _texel_centres(region)
+    n, amb = check_linear_valid(np.stack([cp["u"], cp["v"]], 1), cp["z"] * 0.01, qx, qy, out["hm_lin"],
+                                out["hm_nn"], 1e-9)
+    assert amb > 100, amb
