@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["ora_recon.c", "ora_unet.c", "ora_splat.c"]
+_SOURCES = ["ora_recon.c", "ora_unet.c", "ora_splat.c", "ora_target.c"]
 _lock = threading.Lock()
 _lib = None
 
@@ -85,6 +85,12 @@ def _load():
             lib.ora_splat.argtypes = [i64, i64, i32, i32, i32, i32, P, P, P, P, i64, P, P]
             lib.ora_resolve.restype = None
             lib.ora_resolve.argtypes = [P, i64, dbl, dbl, P]
+            lib.ora_splat_mean.restype = i64
+            lib.ora_splat_mean.argtypes = [i64, i64, i32, i32, i32, i32, P, P, P, P, i64, P, P]
+            lib.ora_resolve_mean.restype = None
+            lib.ora_resolve_mean.argtypes = [P, i64, dbl, dbl, P]
+            lib.ora_target_loss.restype = ctypes.c_int
+            lib.ora_target_loss.argtypes = [P, P, P, i32, i32, dbl, ctypes.c_int, P, P]
             _lib = lib
     return _lib
 
@@ -275,3 +281,54 @@ def resolve(keys, tex, scale_z: float, offset_z: float) -> np.ndarray:
     out = np.array(tex, dtype=np.float32, copy=True, order="C")
     lib.ora_resolve(_p(keys), keys.size, scale_z, offset_z, _p(out))
     return out
+
+
+def splat_mean(region, x, y, z, rgb, tile_slot, n_slots: int, acc=None):
+    """Ground-truth accumulation (Section 3.4, training data): per texel the
+    sums of raw heights and 16-bit colours and the point count, in input
+    order.  Returns (acc int64 [n_slots][res][res][5] = (sum z, sum R, sum G,
+    sum B, count), dropped)."""
+    lib = _load()
+    x, y, z = _c(x, np.int32), _c(y, np.int32), _c(z, np.int32)
+    rgb = _c(np.asarray(rgb).reshape(-1, 3), np.uint16)
+    ts = _c(tile_slot, np.int32)
+    res = region.res
+    if acc is None:
+        acc = np.zeros((n_slots, res, res, 5), np.int64)
+    else:
+        acc = _c(acc, np.int64).copy()
+    dropped = lib.ora_splat_mean(region.origin_x, region.origin_y, region.tile_size, res, region.tiles_x,
+                                 region.tiles_y, _p(x), _p(y), _p(z), _p(rgb), x.size, _p(ts), _p(acc))
+    return acc, int(dropped)
+
+
+def resolve_mean(acc, scale_z: float, offset_z: float) -> np.ndarray:
+    """Mean texture [..., 4] (height in metres, colour in [0, 1]) from the
+    sums; texels without points are NaN (gaps in the ground truth)."""
+    lib = _load()
+    acc = _c(acc, np.int64)
+    n_cells = acc.size // 5
+    out = np.empty(acc.shape[:-1] + (4,), np.float32)
+    lib.ora_resolve_mean(_p(acc), n_cells, scale_z, offset_z, _p(out))
+    return out
+
+
+LOSS_CLIPPED_MSE, LOSS_L1 = 0, 1
+
+
+def target_loss(y, tex, cz, region, kind: int = LOSS_CLIPPED_MSE):
+    """Training loss of the normalised output y [n][res][res][4] against the
+    target texture tex (metres / [0, 1], NaN = gap) (Section 3.4, training).
+    Returns ((L, L_h, L_rgb), dL/dy as float64 [n][res][res][4])."""
+    lib = _load()
+    y = _c(y, np.float32)
+    tex = _c(tex, np.float32)
+    cz = _c(cz, np.float64)
+    n, res = y.shape[0], y.shape[1]
+    r_m = (region.tile_size // 2 + region.pad * region.cell) * region.scale_xy
+    out = np.zeros(3)
+    grad = np.zeros(y.shape)
+    rc = lib.ora_target_loss(_p(y), _p(tex), _p(cz), n, res, r_m, kind, _p(out), _p(grad))
+    if rc:
+        raise ValueError("unknown loss kind")
+    return tuple(float(v) for v in out), grad
