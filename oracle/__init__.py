@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["ora_recon.c", "ora_unet.c", "ora_splat.c", "ora_target.c"]
+_SOURCES = ["ora_recon.c", "ora_unet.c", "ora_splat.c", "ora_target.c", "ora_raster.c"]
 _lock = threading.Lock()
 _lib = None
 
@@ -91,6 +91,10 @@ def _load():
             lib.ora_resolve_mean.argtypes = [P, i64, dbl, dbl, P]
             lib.ora_target_loss.restype = ctypes.c_int
             lib.ora_target_loss.argtypes = [P, P, P, i32, i32, dbl, ctypes.c_int, P, P]
+            lib.ora_raster.restype = i64
+            lib.ora_raster.argtypes = [P, i64, i64, dbl, dbl, dbl, i32, i32, P, P, P, P, i64, P]
+            lib.ora_raster_resolve.restype = None
+            lib.ora_raster_resolve.argtypes = [P, i64, P]
             _lib = lib
     return _lib
 
@@ -332,3 +336,31 @@ def target_loss(y, tex, cz, region, kind: int = LOSS_CLIPPED_MSE):
     if rc:
         raise ValueError("unknown loss kind")
     return tuple(float(v) for v in out), grad
+
+
+def raster(M, origin, scale_xy: float, scale_z: float, offset_z: float, width: int, height: int, x, y, z, rgb,
+           fb=None):
+    """Point rasteriser (Section 3.6): nearest point per pixel through packed
+    64-bit depth-and-colour keys.  M: 4 x 4 view-projection (row-major) on
+    metres relative to origin = (ox, oy) raw.  Returns (fb uint64 [height][width],
+    points drawn); fb accumulates when given (empty pixel = all ones)."""
+    lib = _load()
+    Mx = _c(np.asarray(M, np.float64).reshape(16), np.float64)
+    x, y, z = _c(x, np.int32), _c(y, np.int32), _c(z, np.int32)
+    rgb = _c(np.asarray(rgb).reshape(-1, 3), np.uint16)
+    if fb is None:
+        fb = np.full((height, width), np.iinfo(np.uint64).max, np.uint64)
+    else:
+        fb = _c(fb, np.uint64).copy()
+    drawn = lib.ora_raster(_p(Mx), int(origin[0]), int(origin[1]), scale_xy, scale_z, offset_z, width, height,
+                           _p(x), _p(y), _p(z), _p(rgb), x.size, _p(fb))
+    return fb, int(drawn)
+
+
+def raster_resolve(fb) -> np.ndarray:
+    """RGBA8 words (alpha 255) of the nearest point per pixel; 0 = empty."""
+    lib = _load()
+    fb = _c(fb, np.uint64)
+    out = np.zeros(fb.shape, np.uint32)
+    lib.ora_raster_resolve(_p(fb), fb.size, _p(out))
+    return out
