@@ -135,6 +135,90 @@ def test_backward_fp32_matches_oracle():
         off += sz
 
 
+def _coord_ratio(g, ref, floor_frac=1e-3):
+    """Per layer: max over its coordinates (weights and bias) of
+    |g - ref| / max(|ref|, floor_frac * max|ref over the layer|)."""
+    out, off = [], 0
+    for name, ci, co in synth.UNET_SHAPES:
+        sz = co * 9 * ci + co
+        a, b = g[off:off + sz], ref[off:off + sz]
+        den = np.maximum(np.abs(b), floor_frac * np.abs(b).max())
+        out.append((name, float((np.abs(a - b) / den).max())))
+        off += sz
+    return out
+
+
+def test_backward_fp32_per_coordinate():
+    """Every coordinate of grad_w (each layer's weights and biases) and of
+    grad_x within 1e-3 of the oracle gradient, relative to the coordinate
+    with a floor of 1e-3 of the layer's largest (Section 3.4 training)."""
+    w, xo, wts, G, *_, gw, gx = _backward_case(ls.FP32)
+    x32 = xo.astype(np.float32).astype(np.float64)
+    gw_ref, gx_ref = oracle.unet_backward(wts.astype(np.float32).astype(np.float64), x32, G, 64, 16, want_gx=True)
+    ratios = _coord_ratio(gw, gw_ref)
+    print("fp32 grad_w worst coordinate per layer: " + " ".join(f"{n} {r:.1e}" for n, r in ratios))
+    for n, r in ratios:
+        assert r <= 1e-3, (n, r)
+    den = np.maximum(np.abs(gx_ref), 1e-3 * np.abs(gx_ref).max())
+    rx = float((np.abs(gx - gx_ref) / den).max())
+    print(f"fp32 grad_x worst coordinate {rx:.1e}")
+    assert rx <= 1e-3
+
+
+def test_backward_fp32_against_finite_differences():
+    """The GPU FP32 gradient against FP64 central differences (h = 1e-6) of
+    the oracle network at 32 random coordinates of every layer (weights and
+    biases) plus 8 random directions, on one unpadded tile; per coordinate
+    |g - fd| <= 1e-3 * max(|fd|, 1e-3 * max|g| over the layer)."""
+    import concurrent.futures as cf
+
+    w = synth.batch_tiles(seed=7, tiles_x=1, tiles_y=1, pad=0)
+    xo, cz, _ = oracle.recon_tiles(w.region, *w.points.numpy(), w.tile_list)
+    x32 = xo.astype(np.float32).astype(np.float64)
+    wts = synth.unet_weights(1, head_std=0.05, bias_std=0.05).astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(11)
+    G = rng.standard_normal((1, 64, 64, 4))
+    g = ls.Grid.of(w.region)
+    gw, _ = ls.refine_backward(torch.from_numpy(wts.astype(np.float32)).cuda(),
+                               torch.from_numpy(x32.astype(np.float32)).cuda(),
+                               torch.from_numpy(G.astype(np.float32)).cuda(), g, ls.FP32)
+    torch.cuda.synchronize()
+    gw = gw.cpu().numpy().astype(np.float64)
+
+    def loss(wv):
+        return float((oracle.unet_forward(wv, x32, 64, 0, nthreads=1) * G).sum())
+
+    h = 1e-6
+    jobs, off = [], 0
+    for name, ci, co in synth.UNET_SHAPES:
+        sz = co * 9 * ci + co
+        # 28 random weights and 4 random biases of the layer
+        ks = np.concatenate([rng.choice(co * 9 * ci, 28, replace=False), co * 9 * ci + rng.choice(co, 4, replace=co < 4)])
+        scale = np.abs(gw[off:off + sz]).max()
+        for k in ks:
+            d = np.zeros_like(wts)
+            d[off + k] = 1.0
+            jobs.append((name, int(k), d, gw[off + k], scale))
+        off += sz
+    for _ in range(8):
+        d = rng.standard_normal(wts.size)
+        d /= np.linalg.norm(d)
+        jobs.append(("direction", -1, d, float(gw @ d), np.abs(gw).max()))
+
+    def fd(job):
+        d = job[2]
+        return (loss(wts + h * d) - loss(wts - h * d)) / (2 * h)
+
+    with cf.ThreadPoolExecutor(max_workers=min(16, len(jobs))) as ex:
+        fds = list(ex.map(fd, jobs))
+    worst = {}
+    for (name, k, _, gk, scale), f in zip(jobs, fds):
+        r = abs(gk - f) / max(abs(f), 1e-3 * scale)
+        worst[name] = max(worst.get(name, 0.0), r)
+        assert r <= 1e-3, (name, k, gk, f)
+    print("fp32 grad vs FD, worst per layer: " + " ".join(f"{n} {r:.1e}" for n, r in worst.items()))
+
+
 def test_backward_saved_activations_equal_recompute():
     w, xo, wts, G, g, xt, wt, gt, wb, gw, gx = _backward_case(ls.FP32, want_gx=False)
     act = torch.empty(ls.act_bytes(g, xt.shape[0], ls.FP32), dtype=torch.uint8, device="cuda")
