@@ -126,6 +126,27 @@ int ls_recon_tiles(const ls_grid* g, const int32_t* x, const int32_t* y, const i
                    int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
                    size_t ws_bytes, void* stream);
 
+/* Allocation-free ls_recon_tiles, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as ls_recon_tiles,
+ * without the workspace: the library uses a fixed array of
+ * LS_RECON_SCRATCH_BYTES in device memory instead, which every device the
+ * call runs on holds until the process ends.  The call allocates nothing.
+ * Limit: LS_ESCRATCH (nothing enqueued) when the inputs need more than the
+ * array with a single persistent workgroup (per point of n about 600 bytes,
+ * per tile of the region 4 bytes, per listed tile 20 bytes, plus 12*R*R
+ * bytes per workgroup: about 80,000 points with the 96 x 96 grid); inputs
+ * that fit run on as many workgroups as the array holds (fewer than
+ * ls_recon_tiles uses when the points fill most of it, so slower).
+ * Every call on one GPU shares its array and leaves its contents behind;
+ * calls that overlap on one GPU (other streams, other threads) race on it,
+ * so serialise them. */
+#define LS_RECON_SCRATCH_BYTES ((size_t)48 << 20)
+int ls_recon_tiles_noalloc(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z,
+                           const uint16_t* rgb, int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order,
+                           float* x_out, double* cz_out, int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap,
+                           int32_t* tile_status, void* stream);
+
 /* Refinement network forward (Section 3.4) on a batch of tiles.
  *  w [num_params] FP32; w_bf16 [num_params] BF16 bit patterns (required
  *    for LS_BF16, from ls_pack_weights_bf16; ignored for LS_FP32).

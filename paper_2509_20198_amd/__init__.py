@@ -21,13 +21,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblidarscout.so")
 
 LS_OK, LS_EINVAL, LS_ERANGE, LS_EHIP, LS_ENOTIMPL, LS_EWORKSPACE, LS_ECAP, LS_ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
+RECON_SCRATCH_BYTES = 48 << 20  # LS_RECON_SCRATCH_BYTES
 TILE_EMPTY, TILE_NN_ONLY, TILE_CAP, TILE_DEGENERATE, TILE_BADID = 1, 2, 4, 8, 16
 FP32, BF16 = 0, 1
 OP_RECON, OP_REFINE, OP_BACKWARD, OP_SPLAT = 0, 1, 2, 3
 ORDER_LIST, ORDER_LONGEST_FIRST = 0, 1
 
 EXPORTS = [
-    "ls_num_params", "ls_workspace_bytes", "ls_act_bytes", "ls_recon_tiles", "ls_refine_tiles",
+    "ls_num_params", "ls_workspace_bytes", "ls_act_bytes", "ls_recon_tiles", "ls_recon_tiles_noalloc",
+    "ls_refine_tiles",
     "ls_refine_backward", "ls_splat_points", "ls_resolve_keys", "ls_pack_weights_bf16",
     "ls_conv_num_configs", "ls_set_conv_config", "ls_get_conv_config", "ls_status_string",
     "ls_last_error", "ls_version", "ls_trace_enable", "ls_trace_count", "ls_trace_record",
@@ -95,6 +97,8 @@ def load_library(path: str = LIB_PATH):
         lib.ls_act_bytes.argtypes = [G, i32, ctypes.c_int]
         lib.ls_recon_tiles.restype = ctypes.c_int
         lib.ls_recon_tiles.argtypes = [G, P, P, P, P, i64, P, i32, i32, P, P, P, P, i64, P, P, sz, P]
+        lib.ls_recon_tiles_noalloc.restype = ctypes.c_int
+        lib.ls_recon_tiles_noalloc.argtypes = [G, P, P, P, P, i64, P, i32, i32, P, P, P, P, i64, P, P]
         lib.ls_refine_tiles.restype = ctypes.c_int
         lib.ls_refine_tiles.argtypes = [P, P, ctypes.c_int, P, P, i32, G, P, P, P, P, sz, P]
         lib.ls_refine_backward.restype = ctypes.c_int
@@ -222,6 +226,44 @@ def recon_tiles(grid, x, y, z, rgb, tile_list, *, order: int = ORDER_LIST, x_out
                             int(order), _ptr(x_out), _ptr(cz_out), _ptr(bin_off), _ptr(bin_idx), int(bin_cap), _ptr(status),
                             _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "ls_recon_tiles")
+    return x_out, cz_out, status
+
+
+def recon_tiles_noalloc(grid, x, y, z, rgb, tile_list, *, order: int = ORDER_LIST, x_out=None, cz_out=None,
+                        bin_off=None, bin_idx=None, bin_cap: int = 0, status=None, stream=None):
+    """recon_tiles through the allocation-free entry point (no workspace: the
+    library's fixed device scratch).  Outputs the caller does not pass are
+    allocated here with torch, before the call."""
+    lib = load_library()
+    g = Grid.of(grid)
+    n = x.numel()
+    nt = tile_list.numel()
+    for name, t in (("x", x), ("y", y), ("z", z)):
+        _need(t, name, (torch.int32,), shape=(n,))
+    _need(rgb, "rgb", U16, shape=(n, 3))
+    _need(tile_list, "tile_list", (torch.int32,))
+    dev = x.device
+    R = g.R
+    if x_out is None:
+        x_out = torch.empty((nt, R, R, 8), dtype=torch.float32, device=dev)
+    if cz_out is None:
+        cz_out = torch.empty(nt, dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.empty(nt, dtype=torch.int32, device=dev)
+    _need(x_out, "x_out", (torch.float32,), shape=(nt, R, R, 8))
+    _need(cz_out, "cz_out", (torch.float64,), shape=(nt,))
+    _need(status, "status", (torch.int32,), shape=(nt,))
+    if (bin_off is None) != (bin_idx is None):
+        raise ValueError("bin_off and bin_idx go together")
+    if bin_off is not None:
+        _need(bin_off, "bin_off", (torch.int32,), shape=(nt + 1,))
+        _need(bin_idx, "bin_idx", (torch.int32,))
+        bin_cap = min(int(bin_cap) if bin_cap else bin_idx.numel(), bin_idx.numel())
+    gc = g.c()
+    rc = lib.ls_recon_tiles_noalloc(ctypes.byref(gc), _ptr(x), _ptr(y), _ptr(z), _ptr(rgb), n, _ptr(tile_list), nt,
+                                    int(order), _ptr(x_out), _ptr(cz_out), _ptr(bin_off), _ptr(bin_idx),
+                                    int(bin_cap), _ptr(status), _stream(stream))
+    _check(rc, "ls_recon_tiles_noalloc")
     return x_out, cz_out, status
 
 

@@ -145,6 +145,24 @@ int ls_recon_tiles(const ls_grid* g, const int32_t* x, const int32_t* y, const i
                        tile_status, ws, ws_bytes, ls_stream(stream));
 }
 
+int ls_recon_tiles_noalloc(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z,
+                           const uint16_t* rgb, int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order,
+                           float* x_out, double* cz_out, int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap,
+                           int32_t* tile_status, void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (order != LS_ORDER_LIST && order != LS_ORDER_LONGEST_FIRST) return LS_ERANGE;
+  if (n < 0 || n_tiles < 0 || n > 0x7fffffffLL) return LS_EINVAL;
+  if (n > 0 && (!x || !y || !z || !rgb)) return LS_EINVAL;
+  if (n_tiles > 0 && (!tile_list || !x_out || !cz_out || !tile_status)) return LS_EINVAL;
+  if ((bin_off == nullptr) != (bin_idx == nullptr)) return LS_EINVAL;
+  if (bin_idx && bin_cap < 0) return LS_EINVAL;
+  if ((int64_t)gi.tx * gi.ty > 0x7fffffffLL) return LS_ERANGE;
+  return ls_recon_noalloc_impl(gi, x, y, z, rgb, n, tile_list, n_tiles, order, x_out, cz_out, bin_off, bin_idx,
+                               bin_cap, tile_status, ls_stream(stream));
+}
+
 int ls_refine_tiles(const float* w, const uint16_t* w_bf16, int precision, const float* x, const double* cz,
                     int32_t n_tiles, const ls_grid* g, float* y_out, float* tex_out, void* act_save, void* ws,
                     size_t ws_bytes, void* stream) {

@@ -127,6 +127,10 @@ int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
                   int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order, float* x_out, double* cz_out,
                   int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap, int32_t* tile_status, void* ws,
                   size_t ws_bytes, hipStream_t st);
+int ls_recon_noalloc_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z,
+                          const uint16_t* rgb, int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order,
+                          float* x_out, double* cz_out, int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap,
+                          int32_t* tile_status, hipStream_t st);
 int ls_splat_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
                   int64_t n, const int32_t* tile_slot, int32_t n_slots, uint64_t* keys, float* tex_inout,
                   uint64_t* n_dropped, hipStream_t st);

@@ -33,6 +33,7 @@
 //           corner padding points taken at infinity), normalised and written
 //           as one NHWC row of 8 FP32 channels.
 #include <algorithm>
+#include <mutex>
 
 #include "ls_common.hpp"
 
@@ -1547,6 +1548,70 @@ int recon_enqueue(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
 size_t ls_recon_ws_bytes(const LsGridInfo& gi, int32_t n_tiles, int64_t n) {
   ReconLayout L;
   return recon_layout(gi, n_tiles, n, nullptr, &L, recon_wg_count(n_tiles));
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the workspace is a fixed array in device memory.
+// Host code never passes the array's name to a kernel (in host code it is a
+// stand-in, not a device address); it takes the address that
+// hipGetSymbolAddress returns on each device, once per device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[LS_RECON_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with the device current).
+int scratch_address(void** out) {
+  int dev = -1;
+  LS_HOST_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) {
+    ls_set_last_message("device ordinal beyond the scratch table");
+    return LS_EHIP;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      ls_set_last_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)", __LINE__);
+      return LS_EHIP;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LS_OK;
+}
+
+}  // namespace
+
+int ls_recon_noalloc_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z,
+                          const uint16_t* rgb, int64_t n, const int32_t* tile_list, int32_t n_tiles, int32_t order,
+                          float* x_out, double* cz_out, int32_t* bin_off, int32_t* bin_idx, int64_t bin_cap,
+                          int32_t* tile_status, hipStream_t st) {
+  if (n_tiles <= 0) return LS_OK;
+  ReconLayout L;
+  const size_t cap = LS_RECON_SCRATCH_BYTES;
+  const size_t one = recon_layout(gi, n_tiles, n, nullptr, &L, 1);
+  if (one > cap) return LS_ESCRATCH;
+  // as many persistent workgroups as the scratch holds (their face and
+  // nearest-point maps are the only part that grows with the count)
+  int nwg = recon_wg_count(n_tiles);
+  if (nwg > 1) {
+    const size_t per_wg = recon_layout(gi, n_tiles, n, nullptr, &L, 2) - one;
+    const int64_t fit = 1 + (int64_t)((cap - one) / (per_wg ? per_wg : 1));
+    if (fit < nwg) nwg = (int)fit;
+    while (nwg > 1 && recon_layout(gi, n_tiles, n, nullptr, &L, nwg) > cap) --nwg;
+  }
+  void* ws = nullptr;
+  const int rc = scratch_address(&ws);
+  if (rc != LS_OK) return rc;
+  return recon_enqueue(gi, x, y, z, rgb, n, tile_list, n_tiles, order, x_out, cz_out, bin_off, bin_idx, bin_cap,
+                       tile_status, ws, nwg, st);
 }
 
 int ls_recon_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,

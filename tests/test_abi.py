@@ -37,7 +37,7 @@ def test_every_declared_symbol_exported(lib):
 def test_host_queries(lib):
     assert ls.num_params() == synth.N_PARAMS == 119844
     assert "gfx950" in ls.version()
-    for rc in (0, -1, -2, -3, -4, -5, -6):
+    for rc in (0, -1, -2, -3, -4, -5, -6, -7):
         assert lib.ls_status_string(rc)
     g = ls.Grid(tiles_x=32, tiles_y=32)
     a = ls.workspace_bytes(ls.OP_RECON, g, 1024, 541141)
