@@ -19,7 +19,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["ora_recon.c", "ora_unet.c", "ora_splat.c", "ora_target.c", "ora_raster.c"]
+_SOURCES = ["ora_recon.c", "ora_unet.c", "ora_splat.c", "ora_target.c", "ora_raster.c", "ora_pnet.c"]
 _lock = threading.Lock()
 _lib = None
 
@@ -94,6 +94,10 @@ def _load():
             lib.ora_raster.restype = i64
             lib.ora_raster.argtypes = [P, i64, i64, dbl, dbl, dbl, i32, i32, P, P, P, P, i64, P]
             lib.ora_raster_resolve.restype = None
+            lib.ora_pnet_num_params.restype = i64
+            lib.ora_pnet_num_params.argtypes = [ctypes.c_int]
+            lib.ora_pnet_forward.restype = ctypes.c_int
+            lib.ora_pnet_forward.argtypes = [P, P, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, ctypes.c_int]
             lib.ora_raster_resolve.argtypes = [P, i64, P]
             _lib = lib
     return _lib
@@ -364,3 +368,24 @@ def raster_resolve(fb) -> np.ndarray:
     out = np.zeros(fb.shape, np.uint32)
     lib.ora_raster_resolve(_p(fb), fb.size, _p(out))
     return out
+
+
+def pnet_num_params(R: int = 96) -> int:
+    """Parameters of the paper's refinement network at padded grid side R."""
+    return int(_load().ora_pnet_num_params(R))
+
+
+def pnet_forward(w, x, res: int, pad: int, nthreads: int = 0) -> np.ndarray:
+    """The paper's refinement network (Section 3.4, architecture paragraph):
+    x [n][R][R][8] -> y [n][res][res][4]."""
+    lib = _load()
+    w = _c(w, np.float64)
+    x = _c(x, np.float64)
+    n = x.shape[0]
+    R = res + 2 * pad
+    if w.size != pnet_num_params(R):
+        raise ValueError(f"expected {pnet_num_params(R)} weights, got {w.size}")
+    y = np.zeros((n, res, res, 4))
+    if lib.ora_pnet_forward(_p(w), _p(x), n, res, pad, _p(y), nthreads or default_threads()):
+        raise ValueError("res + 2*pad must be a multiple of 16")
+    return y

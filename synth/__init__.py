@@ -326,8 +326,8 @@ class SparseWorkload:
 
 def sparse_workload(name: str, tiles_x: int, tiles_y: int, counts: np.ndarray, seed: int,
                     order: str = "desc", viewpoint=None, pad: int = 16, res: int = 64,
-                    device="cpu") -> SparseWorkload:
-    region = Region(tiles_x=tiles_x, tiles_y=tiles_y, pad=pad, res=res)
+                    device="cpu", tile_size: int = 64000) -> SparseWorkload:
+    region = Region(tiles_x=tiles_x, tiles_y=tiles_y, pad=pad, res=res, tile_size=tile_size)
     ids = np.arange(tiles_x * tiles_y, dtype=np.int64)
     ps = _points_in_tiles(region, ids, counts, seed, terrain_seed=seed, noise_sigma_m=0.0, device=device)
     ps = shuffle(ps, seed ^ 0xABCDEF)
@@ -398,3 +398,41 @@ def fullres_uniform(region: Region, n: int, seed: int, noise_sigma_m: float = 0.
         zm = zm + noise_sigma_m * gaussian(seed ^ 0x5EED, k)
     ps = PointSet(x.to(torch.int32), y.to(torch.int32), torch.round(zm * 100.0).to(torch.int32), ramp_rgb(zm))
     return morton_sort(ps, region, seed ^ 0x77)
+
+
+# ----------------------------------------------------------------------------
+# the paper's refinement network: layer list and random initialisation
+# ----------------------------------------------------------------------------
+def pnet_layers(R: int = 96):
+    """[(name, kind, cin, cout)] in weight order; kind "conv" (3x3) or "fc"."""
+    F = (R // 16) ** 2 * 32
+    out = []
+    for i, (nm, c0) in enumerate((("hlin", 1), ("hnn", 1), ("rgblin", 3), ("rgbnn", 3))):
+        ch = [c0, 16, 32, 32, 32]
+        out += [(f"enc_{nm}{k + 1}", "conv", ch[k], ch[k + 1]) for k in range(4)]
+    out += [("fc1_h", "fc", 2 * F, 256), ("fc1_c", "fc", 2 * F, 256), ("fc2_h", "fc", 512, F), ("fc2_t", "fc", 512, F)]
+    d = [32, 32, 32, 16, 16]
+    out += [(f"dec_h{k + 1}", "conv", d[k], d[k + 1]) for k in range(4)]
+    out += [(f"dec_t{k + 1}", "conv", d[k], d[k + 1]) for k in range(4)]
+    out += [("fin1", "conv", 40, 32), ("fin2", "conv", 32, 32), ("fin3", "conv", 32, 4)]
+    return out
+
+
+def pnet_layer_size(kind: str, cin: int, cout: int) -> int:
+    return cout * 9 * cin + cout if kind == "conv" else cout * cin + cout
+
+
+def pnet_weights(seed: int = 0, R: int = 96, final_std: Optional[float] = None, bias_std: float = 0.0) -> np.ndarray:
+    """Kaiming-normal (fan_in, gain sqrt 2) hidden layers, small-normal final
+    layer (default 0.01 / sqrt(288)), biases 0 (or N(0, bias_std^2))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    layers = pnet_layers(R)
+    for name, kind, ci, co in layers:
+        fan_in = 9 * ci if kind == "conv" else ci
+        std = (0.01 / math.sqrt(288.0) if final_std is None else final_std) if name == "fin3" \
+            else math.sqrt(2.0 / fan_in)
+        n_w = co * 9 * ci if kind == "conv" else co * ci
+        parts.append(rng.standard_normal(n_w) * std)
+        parts.append(rng.standard_normal(co) * bias_std if bias_std > 0 else np.zeros(co))
+    return np.concatenate(parts)
