@@ -83,7 +83,14 @@ typedef enum ls_precision { LS_FP32 = 0, LS_BF16 = 1 } ls_precision;
  * Results per output slot do not depend on the order. */
 typedef enum ls_order { LS_ORDER_LIST = 0, LS_ORDER_LONGEST_FIRST = 1 } ls_order;
 
-typedef enum ls_op { LS_OP_RECON = 0, LS_OP_REFINE = 1, LS_OP_BACKWARD = 2, LS_OP_SPLAT = 3 } ls_op;
+typedef enum ls_op {
+  LS_OP_RECON = 0,
+  LS_OP_REFINE = 1,
+  LS_OP_BACKWARD = 2,
+  LS_OP_SPLAT = 3,
+  LS_OP_LOSS = 4,
+  LS_OP_REFINE_LSNET = 5
+} ls_op;
 
 /* Number of network parameters (119,844 for the 3-level U-Net).
  * Flat FP32 layout, layers in order enc1a 8->16, enc1b 16->16, enc2a 16->32,
@@ -163,6 +170,42 @@ int ls_refine_tiles(const float* w, const uint16_t* w_bf16, int precision, const
                     int32_t n_tiles, const ls_grid* g, float* y_out, float* tex_out, void* act_save, void* ws,
                     size_t ws_bytes, void* stream);
 
+/* The paper's own refinement network (Section 3.4, architecture paragraph):
+ * every input (h_lin, h_nn, rgb_lin, rgb_nn) has its own encoder of four
+ * conv3x3 + ReLU + 2x2 average-pool layers (c -> 16 -> 32 -> 32 -> 32); two
+ * fully connected layers merge the height features [F_hlin, F_hnn] and the
+ * colour features [F_rgblin, F_rgbnn] into 256 values each (ReLU); two more
+ * (ReLU) map the 512 merged values to the R/16 x R/16 x 32 inputs of a
+ * height decoder and a texture decoder, each four times nearest x2
+ * upsampling + conv3x3 + ReLU (32 -> 32 -> 32 -> 16 -> 16); the original
+ * inputs are concatenated with both decoder outputs (40 channels) and a
+ * final CNN (conv3x3 40 -> 32 ReLU, 32 -> 32 ReLU, 32 -> 4) is evaluated on
+ * the centre res x res crop and added to the crop of the linear input, as
+ * ls_refine_tiles does.  The layer sizes are this library's reading of the
+ * paper's description (its figure is missing): 2,528,708 parameters at
+ * R = 96 ("about 2.5 M").  Requires R % 16 == 0.
+ * Flat FP32 weights, layers in the order enc_hlin1..4, enc_hnn1..4,
+ * enc_rgblin1..4, enc_rgbnn1..4, fc1_h (2L -> 256), fc1_c (2L -> 256),
+ * fc2_h (512 -> L), fc2_t (512 -> L), dec_h1..4, dec_t1..4, fin1, fin2, fin3
+ * with L = (R/16)^2 * 32; conv layers W[Cout][3][3][Cin] then b[Cout];
+ * fully connected W[N][K] then b[N], K indexing the concatenated input, the
+ * feature images flattened in (row, column, channel) order and the FC2
+ * outputs read as (row, column, channel) images.
+ * Returns the parameter count, or -1 for an invalid grid or R % 16 != 0. */
+int64_t ls_lsnet_num_params(const ls_grid* g);
+
+/* Forward of that network on a batch: same x, cz, y_out, tex_out as
+ * ls_refine_tiles.  LS_FP32: FP32 operands and accumulation; LS_BF16: the
+ * FP32 weights rounded to BF16 (nearest even) inside the call, BF16
+ * operands on the matrix cores with FP32 accumulation, every stored hidden
+ * activation BF16, the final layer, residual and denormalisation FP32.
+ *  ws: ls_workspace_bytes(LS_OP_REFINE_LSNET, g, n_tiles, 0, precision)
+ *    bytes (bounded: the batch is processed in chunks).
+ * Errors: LS_ERANGE for R % 16 != 0 or another precision; LS_EINVAL for
+ * null w or x (n_tiles > 0), or tex_out without cz; LS_EWORKSPACE. */
+int ls_lsnet_refine_tiles(const float* w, int precision, const float* x, const double* cz, int32_t n_tiles,
+                          const ls_grid* g, float* y_out, float* tex_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Refinement network backward, for training the network (Section 3.4,
  * training paragraph: the network is fitted to ground-truth heightmaps with a
  * loss on its normalised output; any loss can be used, the caller supplies
@@ -199,6 +242,87 @@ int ls_splat_points(const ls_grid* g, const int32_t* x, const int32_t* y, const 
 
 /* Resolve only (the second half of ls_splat_points). */
 int ls_resolve_keys(const ls_grid* g, const uint64_t* keys, int32_t n_slots, float* tex_inout, void* stream);
+
+/* Ground-truth accumulation for training (Section 3.4, training data: each
+ * ground-truth heightmap and texture is the per-texel average of all points
+ * that fall on the texel).  Every point with texel gx = floor((x -
+ * origin_x)/cell), gy likewise, inside the region and in a tile whose
+ * tile_slot[ty*tiles_x + tx] >= 0, adds
+ *   acc[slot][gy % res][gx % res] += (z, R, G, B, 1)
+ * with z the raw int32 height and R, G, B the 16-bit colours.  acc
+ * [n_slots][res][res][5] int64 (sum z, sum R, sum G, sum B, count)
+ * accumulates across calls (the caller zeroes it once); integer sums, so
+ * the result is exact for any point order.  *n_dropped (device, uint64) is
+ * incremented by the points outside the region or in unmapped tiles.
+ * Errors: LS_EINVAL for n > 0 with a null array; LS_ERANGE for a grid whose
+ * texel extent times the cell exceeds 2^31. */
+int ls_splat_mean(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                  int64_t n, const int32_t* tile_slot, int32_t n_slots, int64_t* acc, uint64_t* n_dropped,
+                  void* stream);
+
+/* Mean texture from ls_splat_mean sums: tex [n_slots][res][res][4] FP32 =
+ * (mean z * scale_z + offset_z metres, mean R/65535, mean G/65535, mean
+ * B/65535), each mean a double division rounded once to FP32 after the
+ * scale (multiply, then add, no contraction); texels with count 0 are NaN in
+ * all four channels (gaps, masked out of the loss). */
+int ls_resolve_mean(const ls_grid* g, const int64_t* acc, int32_t n_slots, float* tex, void* stream);
+
+/* Loss kinds of ls_target_loss. */
+typedef enum ls_loss {
+  LS_LOSS_CLIPPED_MSE = 0, /* Section 3.4 training: squared error clipped to [0, 1], NaN targets masked */
+  LS_LOSS_L1 = 1           /* mean absolute error */
+} ls_loss;
+
+/* Training loss of the normalised network output against a target texture
+ * (Section 3.4, training: a mean squared error in which elements with a NaN
+ * ground truth are ignored, the errors clipped to [0, 1], the height and
+ * texture losses averaged).
+ *  y [n_tiles][res][res][4] FP32: network output (h, r, g, b), normalised.
+ *  t [n_tiles][res][res][4] FP32: target texture, height in metres, colour
+ *    in [0, 1], NaN = no ground truth; its height is normalised like the
+ *    input, (t_h - cz[tile]) / r with r = H*scale_xy.
+ *  cz [n_tiles] FP64 (from ls_recon_tiles).
+ *  Per element d = y - target (double): LS_LOSS_CLIPPED_MSE e = min(d^2, 1),
+ *  gradient d/N where d^2 <= 1, else 0; LS_LOSS_L1 e = |d|, gradient
+ *  sign(d)/(2N) (sign(0) = 0).  N = n_tiles*res*res for heights and three
+ *  times that for colours; L_h = sum e_h / N_h, L_rgb = sum e_rgb / N_rgb,
+ *  L = (L_h + L_rgb) / 2.  NaN targets give e = 0 and gradient 0.
+ *  loss_out [3] FP64 (device): L, L_h, L_rgb; the sums are reduced in a
+ *    fixed order (deterministic).
+ *  grad (nullable) [n_tiles][res][res][4] FP32: dL/dy, rounded once.
+ *  ws: ls_workspace_bytes(LS_OP_LOSS, ...) bytes.
+ * Errors: LS_EINVAL for null y, t, cz or loss_out; LS_ERANGE for another
+ * kind; LS_EWORKSPACE for a short workspace. */
+int ls_target_loss(const float* y, const float* t, const double* cz, int32_t n_tiles, const ls_grid* g, int kind,
+                   double* loss_out, float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* View of the point rasteriser (host). */
+typedef struct ls_view {
+  double m[16];                /* view-projection, row-major: clip = m * (X, Y, Z, 1) */
+  int64_t origin_x, origin_y;  /* raw units; X = (x - origin_x)*scale_xy, Y likewise (metres) */
+  double scale_xy, scale_z, offset_z; /* Z = z*scale_z + offset_z (metres) */
+  int32_t width, height;       /* frame buffer size in pixels */
+} ls_view;
+
+/* Point rasteriser (Section 3.6, points: depth and colour packed into one
+ * 64-bit integer per point, the nearest kept per pixel by a 64-bit atomic
+ * minimum, then a resolve pass).  Per point, in double precision without
+ * contraction: clip rows c_r = ((m[4r]*X + m[4r+1]*Y) + m[4r+2]*Z) + m[4r+3];
+ * drawn iff w = c_3 > 0 and ndc = (c_0/w, c_1/w) in [-1, 1)^2; pixel column
+ * floor(((ndc_x + 1)*0.5)*width), row likewise (row 0 at ndc_y = -1);
+ *   key = bits((float)w) << 32 | 0xFF << 24 | B8 << 16 | G8 << 8 | R8
+ * (C8 = C16 >> 8), fb[row][col] = min(fb, key).
+ *  fb [height][width] uint64, in/out: the caller fills it with all ones
+ *    (empty) and it accumulates across calls; bit-exact for any order.
+ *  n_drawn (nullable, device uint64): incremented by the points drawn.
+ * Errors: LS_EINVAL for a null view, or n > 0 with a null array or fb;
+ * LS_ERANGE for width or height outside [1, 32768]. */
+int ls_raster_points(const ls_view* v, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                     int64_t n, uint64_t* fb, uint64_t* n_drawn, void* stream);
+
+/* Resolve of the rasteriser: rgba[i] = low 32 bits of fb[i] (R8 | G8 << 8 |
+ * B8 << 16 | 0xFF << 24), 0 for an empty pixel (all ones). */
+int ls_raster_resolve(const uint64_t* fb, int64_t n_pixels, uint32_t* rgba, void* stream);
 
 /* FP32 -> BF16 (round to nearest even) weight copy for LS_BF16. */
 int ls_pack_weights_bf16(const float* w, uint16_t* w_bf16, void* stream);

@@ -24,7 +24,8 @@ LS_OK, LS_EINVAL, LS_ERANGE, LS_EHIP, LS_ENOTIMPL, LS_EWORKSPACE, LS_ECAP, LS_ES
 RECON_SCRATCH_BYTES = 48 << 20  # LS_RECON_SCRATCH_BYTES
 TILE_EMPTY, TILE_NN_ONLY, TILE_CAP, TILE_DEGENERATE, TILE_BADID = 1, 2, 4, 8, 16
 FP32, BF16 = 0, 1
-OP_RECON, OP_REFINE, OP_BACKWARD, OP_SPLAT = 0, 1, 2, 3
+OP_RECON, OP_REFINE, OP_BACKWARD, OP_SPLAT, OP_LOSS, OP_REFINE_LSNET = 0, 1, 2, 3, 4, 5
+LOSS_CLIPPED_MSE, LOSS_L1 = 0, 1
 ORDER_LIST, ORDER_LONGEST_FIRST = 0, 1
 
 EXPORTS = [
@@ -33,6 +34,8 @@ EXPORTS = [
     "ls_refine_backward", "ls_splat_points", "ls_resolve_keys", "ls_pack_weights_bf16",
     "ls_conv_num_configs", "ls_set_conv_config", "ls_get_conv_config", "ls_status_string",
     "ls_last_error", "ls_version", "ls_trace_enable", "ls_trace_count", "ls_trace_record",
+    "ls_splat_mean", "ls_resolve_mean", "ls_target_loss", "ls_raster_points", "ls_raster_resolve",
+    "ls_lsnet_num_params", "ls_lsnet_refine_tiles",
 ]
 
 
@@ -41,6 +44,12 @@ class LsGrid(ctypes.Structure):
                 ("res", ctypes.c_int32), ("pad", ctypes.c_int32), ("tiles_x", ctypes.c_int32),
                 ("tiles_y", ctypes.c_int32), ("scale_xy", ctypes.c_double), ("scale_z", ctypes.c_double),
                 ("offset_z", ctypes.c_double)]
+
+
+class LsView(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_double * 16), ("origin_x", ctypes.c_int64), ("origin_y", ctypes.c_int64),
+                ("scale_xy", ctypes.c_double), ("scale_z", ctypes.c_double), ("offset_z", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
 
 
 @dataclass
@@ -107,6 +116,20 @@ def load_library(path: str = LIB_PATH):
         lib.ls_splat_points.argtypes = [G, P, P, P, P, i64, P, i32, P, P, P, P]
         lib.ls_resolve_keys.restype = ctypes.c_int
         lib.ls_resolve_keys.argtypes = [G, P, i32, P, P]
+        lib.ls_splat_mean.restype = ctypes.c_int
+        lib.ls_splat_mean.argtypes = [G, P, P, P, P, i64, P, i32, P, P, P]
+        lib.ls_resolve_mean.restype = ctypes.c_int
+        lib.ls_resolve_mean.argtypes = [G, P, i32, P, P]
+        lib.ls_target_loss.restype = ctypes.c_int
+        lib.ls_target_loss.argtypes = [P, P, P, i32, G, ctypes.c_int, P, P, P, sz, P]
+        lib.ls_raster_points.restype = ctypes.c_int
+        lib.ls_raster_points.argtypes = [ctypes.POINTER(LsView), P, P, P, P, i64, P, P, P]
+        lib.ls_raster_resolve.restype = ctypes.c_int
+        lib.ls_raster_resolve.argtypes = [P, i64, P, P]
+        lib.ls_lsnet_num_params.restype = i64
+        lib.ls_lsnet_num_params.argtypes = [G]
+        lib.ls_lsnet_refine_tiles.restype = ctypes.c_int
+        lib.ls_lsnet_refine_tiles.argtypes = [P, ctypes.c_int, P, P, i32, G, P, P, P, sz, P]
         lib.ls_pack_weights_bf16.restype = ctypes.c_int
         lib.ls_pack_weights_bf16.argtypes = [P, P, P]
         lib.ls_conv_num_configs.restype = ctypes.c_int
@@ -315,6 +338,46 @@ def refine_tiles(w, x, cz, grid, precision: int = FP32, *, w_bf16=None, y_out=No
     return y_out, tex_out
 
 
+def lsnet_num_params(grid) -> int:
+    """Parameters of the paper's refinement network at the grid's padded side (2,528,708 at 96)."""
+    g = Grid.of(grid).c()
+    n = int(load_library().ls_lsnet_num_params(ctypes.byref(g)))
+    if n < 0:
+        raise LidarScoutError("the paper's network needs res + 2*pad divisible by 16")
+    return n
+
+
+def lsnet_refine_tiles(w, x, cz, grid, precision: int = FP32, *, y_out=None, tex_out=None, want_y: bool = True,
+                       want_tex: bool = True, ws=None, stream=None):
+    """The paper's refinement network forward -> (y [n,res,res,4], tex [n,res,res,4]) (either may be None)."""
+    lib = load_library()
+    g = Grid.of(grid)
+    P = lsnet_num_params(g)
+    nt = x.shape[0]
+    R, res = g.R, g.res
+    _need(w, "w", (torch.float32,), shape=(P,))
+    _need(x, "x", (torch.float32,), shape=(nt, R, R, 8))
+    dev = x.device
+    if y_out is None and want_y:
+        y_out = torch.empty((nt, res, res, 4), dtype=torch.float32, device=dev)
+    if tex_out is None and want_tex:
+        tex_out = torch.empty((nt, res, res, 4), dtype=torch.float32, device=dev)
+    if y_out is not None:
+        _need(y_out, "y_out", (torch.float32,), shape=(nt, res, res, 4))
+    if tex_out is not None:
+        _need(tex_out, "tex_out", (torch.float32,), shape=(nt, res, res, 4))
+        _need(cz, "cz", (torch.float64,), shape=(nt,))
+    need = workspace_bytes(OP_REFINE_LSNET, g, nt, 0, precision)
+    if ws is None:
+        ws = alloc_workspace(need, dev)
+    _need(ws, "ws", (torch.uint8,), numel=need)
+    gc = g.c()
+    rc = lib.ls_lsnet_refine_tiles(_ptr(w), precision, _ptr(x), _ptr(cz), nt, ctypes.byref(gc), _ptr(y_out),
+                                   _ptr(tex_out), _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "ls_lsnet_refine_tiles")
+    return y_out, tex_out
+
+
 def refine_backward(w, x, grad_y, grid, precision: int = FP32, *, w_bf16=None, act_save=None, grad_w=None,
                     want_grad_x: bool = False, grad_x=None, ws=None, stream=None):
     """Backward of refine_tiles -> (grad_w [P], grad_x [n,R,R,8] or None)."""
@@ -420,6 +483,127 @@ def resolve_keys(grid, keys, tex_inout, stream=None):
     _check(lib.ls_resolve_keys(ctypes.byref(gc), _ptr(keys), n_slots, _ptr(tex_inout), _stream(stream)),
            "ls_resolve_keys")
     return tex_inout
+
+
+def splat_mean(grid, x, y, z, rgb, tile_slot, n_slots: int, acc=None, n_dropped=None, stream=None):
+    """Ground-truth sums per texel -> (acc [n_slots,res,res,5] int64 = (sum z, sum R, sum G, sum B,
+    count), n_dropped [1]); acc accumulates when given."""
+    lib = load_library()
+    g = Grid.of(grid)
+    n = x.numel()
+    for name, t in (("x", x), ("y", y), ("z", z)):
+        _need(t, name, (torch.int32,), shape=(n,))
+    _need(rgb, "rgb", U16, shape=(n, 3))
+    _need(tile_slot, "tile_slot", (torch.int32,), shape=(g.tiles_x * g.tiles_y,))
+    dev = x.device
+    if acc is None:
+        acc = torch.zeros((n_slots, g.res, g.res, 5), dtype=torch.int64, device=dev)
+    _need(acc, "acc", (torch.int64,), shape=(n_slots, g.res, g.res, 5))
+    if n_dropped is None:
+        n_dropped = torch.zeros(1, dtype=torch.int64, device=dev)
+    _need(n_dropped, "n_dropped", (torch.int64, torch.uint64), shape=(1,))
+    gc = g.c()
+    rc = lib.ls_splat_mean(ctypes.byref(gc), _ptr(x), _ptr(y), _ptr(z), _ptr(rgb), n, _ptr(tile_slot), n_slots,
+                           _ptr(acc), _ptr(n_dropped), _stream(stream))
+    _check(rc, "ls_splat_mean")
+    return acc, n_dropped
+
+
+def resolve_mean(grid, acc, tex=None, stream=None):
+    """Mean texture [n_slots,res,res,4] (metres, [0, 1]; NaN where no point) from splat_mean sums."""
+    lib = load_library()
+    g = Grid.of(grid)
+    n_slots = acc.shape[0]
+    _need(acc, "acc", (torch.int64,), shape=(n_slots, g.res, g.res, 5))
+    if tex is None:
+        tex = torch.empty((n_slots, g.res, g.res, 4), dtype=torch.float32, device=acc.device)
+    _need(tex, "tex", (torch.float32,), shape=(n_slots, g.res, g.res, 4))
+    gc = g.c()
+    _check(lib.ls_resolve_mean(ctypes.byref(gc), _ptr(acc), n_slots, _ptr(tex), _stream(stream)), "ls_resolve_mean")
+    return tex
+
+
+def target_loss(y, t, cz, grid, kind: int = LOSS_CLIPPED_MSE, *, want_grad: bool = True, loss_out=None, grad=None,
+                ws=None, stream=None):
+    """Training loss of the normalised output y against the target texture t (NaN = no target)
+    -> (loss [3] float64 on the device = (L, L_h, L_rgb), dL/dy [n,res,res,4] or None)."""
+    lib = load_library()
+    g = Grid.of(grid)
+    nt = y.shape[0]
+    res = g.res
+    _need(y, "y", (torch.float32,), shape=(nt, res, res, 4))
+    _need(t, "t", (torch.float32,), shape=(nt, res, res, 4))
+    _need(cz, "cz", (torch.float64,), shape=(nt,))
+    dev = y.device
+    if loss_out is None:
+        loss_out = torch.empty(3, dtype=torch.float64, device=dev)
+    _need(loss_out, "loss_out", (torch.float64,), shape=(3,))
+    if grad is None and want_grad:
+        grad = torch.empty_like(y)
+    if grad is not None:
+        _need(grad, "grad", (torch.float32,), shape=(nt, res, res, 4))
+    need = workspace_bytes(OP_LOSS, g, nt)
+    if ws is None:
+        ws = alloc_workspace(need, dev)
+    _need(ws, "ws", (torch.uint8,), numel=need)
+    gc = g.c()
+    rc = lib.ls_target_loss(_ptr(y), _ptr(t), _ptr(cz), nt, ctypes.byref(gc), int(kind), _ptr(loss_out), _ptr(grad),
+                            _ptr(ws), ws.numel(), _stream(stream))
+    _check(rc, "ls_target_loss")
+    return loss_out, grad
+
+
+@dataclass
+class View:
+    """Point-rasteriser view (mirror of ls_view): m is the 4 x 4 row-major view-projection on metres
+    relative to (origin_x, origin_y)."""
+    m: tuple
+    origin_x: int = 0
+    origin_y: int = 0
+    scale_xy: float = 0.01
+    scale_z: float = 0.01
+    offset_z: float = 0.0
+    width: int = 1024
+    height: int = 1024
+
+    def c(self) -> LsView:
+        m = [float(v) for v in (self.m.reshape(-1) if hasattr(self.m, "reshape") else self.m)]
+        if len(m) != 16:
+            raise ValueError("view matrix must have 16 entries")
+        return LsView((ctypes.c_double * 16)(*m), int(self.origin_x), int(self.origin_y), float(self.scale_xy),
+                      float(self.scale_z), float(self.offset_z), int(self.width), int(self.height))
+
+
+def raster_points(view: View, x, y, z, rgb, fb=None, n_drawn=None, stream=None):
+    """Nearest point per pixel via packed 64-bit keys -> (fb [height,width] int64 bits, n_drawn [1]);
+    a new fb starts all ones (empty), a given one accumulates."""
+    lib = load_library()
+    n = x.numel()
+    for name, t in (("x", x), ("y", y), ("z", z)):
+        _need(t, name, (torch.int32,), shape=(n,))
+    _need(rgb, "rgb", U16, shape=(n, 3))
+    dev = x.device
+    if fb is None:
+        fb = torch.full((view.height, view.width), -1, dtype=torch.int64, device=dev)
+    _need(fb, "fb", (torch.int64, torch.uint64), shape=(view.height, view.width))
+    if n_drawn is None:
+        n_drawn = torch.zeros(1, dtype=torch.int64, device=dev)
+    _need(n_drawn, "n_drawn", (torch.int64, torch.uint64), shape=(1,))
+    vc = view.c()
+    rc = lib.ls_raster_points(ctypes.byref(vc), _ptr(x), _ptr(y), _ptr(z), _ptr(rgb), n, _ptr(fb), _ptr(n_drawn),
+                              _stream(stream))
+    _check(rc, "ls_raster_points")
+    return fb, n_drawn
+
+
+def raster_resolve(fb, rgba=None, stream=None):
+    """RGBA8 words [height,width] (int32 bits; 0 = empty pixel) of a raster_points frame buffer."""
+    _need(fb, "fb", (torch.int64, torch.uint64))
+    if rgba is None:
+        rgba = torch.empty(fb.shape, dtype=torch.int32, device=fb.device)
+    _need(rgba, "rgba", (torch.int32, torch.uint32), shape=tuple(fb.shape))
+    _check(load_library().ls_raster_resolve(_ptr(fb), fb.numel(), _ptr(rgba), _stream(stream)), "ls_raster_resolve")
+    return rgba
 
 
 def set_conv_config(layer: int, precision: int, pass_: int, config: int):

@@ -117,6 +117,9 @@ size_t ls_workspace_bytes(int op, const ls_grid* g, int32_t n_tiles, int64_t n_p
     case LS_OP_RECON: return ls_recon_ws_bytes(gi, n_tiles, n_points);
     case LS_OP_REFINE: return ls_refine_ws_bytes(gi, n_tiles, precision, 0);
     case LS_OP_BACKWARD: return ls_refine_ws_bytes(gi, n_tiles, precision, 1);
+    case LS_OP_LOSS: return ls_loss_ws_bytes();
+    case LS_OP_REFINE_LSNET:
+      return (precision == LS_FP32 || precision == LS_BF16) ? ls_lsnet_ws_bytes(gi, n_tiles, precision) : 0;
     default: return 0;
   }
 }
@@ -178,6 +181,25 @@ int ls_refine_tiles(const float* w, const uint16_t* w_bf16, int precision, const
                                 ls_stream(stream));
 }
 
+int64_t ls_lsnet_num_params(const ls_grid* g) {
+  LsGridInfo gi;
+  if (ls_grid_info(g, &gi) != LS_OK) return -1;
+  return ls_lsnet_params(gi.R);
+}
+
+int ls_lsnet_refine_tiles(const float* w, int precision, const float* x, const double* cz, int32_t n_tiles,
+                          const ls_grid* g, float* y_out, float* tex_out, void* ws, size_t ws_bytes, void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (gi.R % 16) return LS_ERANGE;
+  if (precision != LS_FP32 && precision != LS_BF16) return LS_ERANGE;
+  if (n_tiles < 0) return LS_EINVAL;
+  if (n_tiles > 0 && (!w || !x)) return LS_EINVAL;
+  if (tex_out && !cz) return LS_EINVAL;
+  return ls_lsnet_forward_impl(w, precision, x, cz, n_tiles, gi, y_out, tex_out, ws, ws_bytes, ls_stream(stream));
+}
+
 int ls_refine_backward(const float* w, const uint16_t* w_bf16, int precision, const float* x,
                        const void* act_save, const float* grad_y, int32_t n_tiles, const ls_grid* g, float* grad_w,
                        float* grad_x, void* ws, size_t ws_bytes, void* stream) {
@@ -210,6 +232,49 @@ int ls_resolve_keys(const ls_grid* g, const uint64_t* keys, int32_t n_slots, flo
   if (rc != LS_OK) return rc;
   if (n_slots < 0 || (n_slots > 0 && (!keys || !tex_inout))) return LS_EINVAL;
   return ls_resolve_impl(gi, keys, n_slots, tex_inout, ls_stream(stream));
+}
+
+int ls_splat_mean(const ls_grid* g, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                  int64_t n, const int32_t* tile_slot, int32_t n_slots, int64_t* acc, uint64_t* n_dropped,
+                  void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (n < 0 || n_slots < 0) return LS_EINVAL;
+  if (n > 0 && (!x || !y || !z || !rgb || !tile_slot || !acc || !n_dropped)) return LS_EINVAL;
+  return ls_splat_mean_impl(gi, x, y, z, rgb, n, tile_slot, n_slots, acc, n_dropped, ls_stream(stream));
+}
+
+int ls_resolve_mean(const ls_grid* g, const int64_t* acc, int32_t n_slots, float* tex, void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (n_slots < 0 || (n_slots > 0 && (!acc || !tex))) return LS_EINVAL;
+  return ls_resolve_mean_impl(gi, acc, n_slots, tex, ls_stream(stream));
+}
+
+int ls_target_loss(const float* y, const float* t, const double* cz, int32_t n_tiles, const ls_grid* g, int kind,
+                   double* loss_out, float* grad, void* ws, size_t ws_bytes, void* stream) {
+  LsGridInfo gi;
+  const int rc = ls_grid_info(g, &gi);
+  if (rc != LS_OK) return rc;
+  if (kind != LS_LOSS_CLIPPED_MSE && kind != LS_LOSS_L1) return LS_ERANGE;
+  if (n_tiles < 0 || !loss_out) return LS_EINVAL;
+  if (n_tiles > 0 && (!y || !t || !cz)) return LS_EINVAL;
+  return ls_target_loss_impl(y, t, cz, n_tiles, gi, kind, loss_out, grad, ws, ws_bytes, ls_stream(stream));
+}
+
+int ls_raster_points(const ls_view* v, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                     int64_t n, uint64_t* fb, uint64_t* n_drawn, void* stream) {
+  if (!v || n < 0) return LS_EINVAL;
+  if (v->width < 1 || v->height < 1 || v->width > 32768 || v->height > 32768) return LS_ERANGE;
+  if (n > 0 && (!x || !y || !z || !rgb || !fb)) return LS_EINVAL;
+  return ls_raster_impl(*v, x, y, z, rgb, n, fb, n_drawn, ls_stream(stream));
+}
+
+int ls_raster_resolve(const uint64_t* fb, int64_t n_pixels, uint32_t* rgba, void* stream) {
+  if (n_pixels < 0 || (n_pixels > 0 && (!fb || !rgba))) return LS_EINVAL;
+  return ls_raster_resolve_impl(fb, n_pixels, rgba, ls_stream(stream));
 }
 
 int ls_pack_weights_bf16(const float* w, uint16_t* w_bf16, void* stream) {

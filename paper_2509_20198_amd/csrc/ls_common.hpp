@@ -135,6 +135,21 @@ int ls_splat_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, cons
                   int64_t n, const int32_t* tile_slot, int32_t n_slots, uint64_t* keys, float* tex_inout,
                   uint64_t* n_dropped, hipStream_t st);
 int ls_resolve_impl(const LsGridInfo& gi, const uint64_t* keys, int32_t n_slots, float* tex_inout, hipStream_t st);
+int ls_splat_mean_impl(const LsGridInfo& gi, const int32_t* x, const int32_t* y, const int32_t* z,
+                       const uint16_t* rgb, int64_t n, const int32_t* tile_slot, int32_t n_slots, int64_t* acc,
+                       uint64_t* n_dropped, hipStream_t st);
+int ls_resolve_mean_impl(const LsGridInfo& gi, const int64_t* acc, int32_t n_slots, float* tex, hipStream_t st);
+size_t ls_loss_ws_bytes();
+int ls_target_loss_impl(const float* y, const float* t, const double* cz, int32_t n_tiles, const LsGridInfo& gi,
+                        int kind, double* loss_out, float* grad, void* ws, size_t ws_bytes, hipStream_t st);
+int ls_raster_impl(const ls_view& v, const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
+                   int64_t n, uint64_t* fb, uint64_t* n_drawn, hipStream_t st);
+int ls_raster_resolve_impl(const uint64_t* fb, int64_t n_pixels, uint32_t* rgba, hipStream_t st);
+int64_t ls_lsnet_params(int R);
+size_t ls_lsnet_ws_bytes(const LsGridInfo& gi, int32_t n_tiles, int precision);
+int ls_lsnet_forward_impl(const float* w, int precision, const float* x, const double* cz, int32_t n_tiles,
+                          const LsGridInfo& gi, float* y_out, float* tex_out, void* ws, size_t ws_bytes,
+                          hipStream_t st);
 int ls_zero_f32(float* p, int64_t n, hipStream_t st);
 int ls_conv_num_configs_impl(int layer, int precision, int pass);
 int ls_conv_config_get(int layer, int precision, int pass);

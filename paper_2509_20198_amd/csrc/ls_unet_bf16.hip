@@ -172,21 +172,6 @@ constexpr int TT = 16;       // output tile side
 constexpr int PT = TT + 2;   // input patch side
 constexpr size_t LDS_MAX = 160 * 1024;  // LDS per workgroup on gfx950
 
-struct ConvTileArgs {
-  ConvSrc src;
-  int B, H, W;           // input plane (zero padding outside)
-  int y0, x0, Ho, Wo;    // output window inside the plane
-  int tiles_x, tiles_y;  // output tiles per image
-  const uint16_t* wp;
-  int Kpad;
-  const float* bias;
-  int cout;
-  int relu;
-  uint16_t* out_bf16;  // [B][Ho][Wo][cout] or null
-  float* out_f32;      // [B][Ho][Wo][cout] or null
-  uint16_t* pool_out;  // [B][Ho/2][Wo/2][cout] or null (Ho, Wo multiples of 16)
-};
-
 __host__ __device__ __forceinline__ int patch_pitch(int cin) {
   const int u = cin / 8;
   return 8 * (u + ((u & 1) ? 0 : 1));  // bf16 elements per pixel, odd number of 16-byte units
@@ -221,8 +206,8 @@ __device__ __forceinline__ void conv_tile_store(const ConvTileArgs& A, f32x4 (&a
       const int pix = e / (cout / 4), c4 = e - pix * (cout / 4);
       const int oy = ty0 + pix / TT, ox = tx0 + pix % TT;
       if (oy >= A.Ho || ox >= A.Wo) continue;
-      *reinterpret_cast<float4*>(A.out_f32 + (((int64_t)b * A.Ho + oy) * A.Wo + ox) * cout + 4 * c4) =
-          *reinterpret_cast<const float4*>(s_of + pix * cout + 4 * c4);
+      *reinterpret_cast<float4*>(A.out_f32 + (((int64_t)b * A.Ho + oy) * A.Wo + ox) * A.out_stride + A.out_coff +
+                                 4 * c4) = *reinterpret_cast<const float4*>(s_of + pix * cout + 4 * c4);
     }
     return;
   }
@@ -248,8 +233,8 @@ __device__ __forceinline__ void conv_tile_store(const ConvTileArgs& A, f32x4 (&a
       const int pix = e / c8n, c8 = e - pix * c8n;
       const int oy = ty0 + pix / TT, ox = tx0 + pix % TT;
       if (oy >= A.Ho || ox >= A.Wo) continue;
-      *reinterpret_cast<u16x8*>(A.out_bf16 + (((int64_t)b * A.Ho + oy) * A.Wo + ox) * cout + 8 * c8) =
-          *reinterpret_cast<const u16x8*>(s_o + pix * cout + 8 * c8);
+      *reinterpret_cast<u16x8*>(A.out_bf16 + (((int64_t)b * A.Ho + oy) * A.Wo + ox) * A.out_stride + A.out_coff +
+                                8 * c8) = *reinterpret_cast<const u16x8*>(s_o + pix * cout + 8 * c8);
     }
   if (A.pool_out) {
     const int Hp = A.Ho / 2, Wp = A.Wo / 2;
@@ -259,7 +244,8 @@ __device__ __forceinline__ void conv_tile_store(const ConvTileArgs& A, f32x4 (&a
       const uint16_t* q = s_o + ((2 * py) * TT + 2 * px) * cout + c;
       const float s = (bf2f(q[0]) + bf2f(q[cout])) + (bf2f(q[TT * cout]) + bf2f(q[TT * cout + cout]));
       const int oy = ty0 / 2 + py, ox = tx0 / 2 + px;
-      A.pool_out[(((int64_t)b * Hp + oy) * Wp + ox) * cout + c] = f2bf(0.25f * s);
+      if (oy >= Hp || ox >= Wp) continue;
+      A.pool_out[(((int64_t)b * Hp + oy) * Wp + ox) * A.pool_stride + A.pool_coff + c] = f2bf(0.25f * s);
     }
   }
 }
@@ -385,6 +371,7 @@ __device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f
   // a whole tile inside the output needs no per-row test
   const bool full = ty0 + TT <= A.Ho && tx0 + TT <= A.Wo;
   const int64_t pix0 = ((int64_t)b * A.Ho + oy0) * A.Wo + ox;  // output pixel of row mt = 0
+  const int ostr = A.out_stride;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     const int c0 = nt * 16 + 4 * g;
@@ -398,7 +385,7 @@ __device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f
         if (A.relu) v = fmaxf(v, 0.f);
         q[mt][r] = v;
       }
-    const int64_t off0 = pix0 * cout + c0, row = (int64_t)A.Wo * cout;
+    const int64_t off0 = pix0 * ostr + A.out_coff + c0, row = (int64_t)A.Wo * ostr;
     if (A.out_f32) {
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
@@ -429,12 +416,13 @@ __device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f
           const float tr = __shfl_xor(tl, 1, 64), br = __shfl_xor(bl, 1, 64);
           pv[r] = f2bf(0.25f * ((tl + tr) + (bl + br)));
         }
-        if ((r16 & 1) == 0) {
-          const int py = (ty0 + wave * 4 + 2 * pr) / 2, px = ox / 2;
+        const int py = (ty0 + wave * 4 + 2 * pr) / 2, px = ox / 2;
+        if ((r16 & 1) == 0 && (full || (py < Hp && px < Wp))) {
           uint2 u;
           u.x = (uint32_t)pv[0] | ((uint32_t)pv[1] << 16);
           u.y = (uint32_t)pv[2] | ((uint32_t)pv[3] << 16);
-          *reinterpret_cast<uint2*>(A.pool_out + (((int64_t)b * Hp + py) * Wp + px) * cout + c0) = u;
+          *reinterpret_cast<uint2*>(A.pool_out + (((int64_t)b * Hp + py) * Wp + px) * A.pool_stride + A.pool_coff +
+                                    c0) = u;
         }
       }
     }
@@ -889,6 +877,10 @@ int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed,
   a.out_bf16 = out_bf16;
   a.out_f32 = out_f32;
   a.pool_out = pool_out;
+  a.out_stride = a.cout;
+  a.out_coff = 0;
+  a.pool_stride = a.cout;
+  a.pool_coff = 0;
   if (pool_out && (Ho % TT || Wo % TT)) return LS_ENOTIMPL;
   const int cin = s.a.c + s.b.c;
   const size_t patch = (size_t)PT * PT * patch_pitch(cin) * 2;
@@ -1071,4 +1063,42 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
                          gi.res, gi.res, variant(10) == 3, st);
   return conv_bf16(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, 0, gi.pad, gi.pad, gi.res, gi.res,
                    variant(10) == 2 ? 2 : 4, st);
+}
+
+int ls_bf16_conv_pipe(const ConvTileArgs& a, int nt, int ca, int cb, bool upa, bool f32a, bool f32b,
+                      hipStream_t st) {
+  if (a.B <= 0 || a.tiles_x <= 0 || a.tiles_y <= 0) return LS_OK;
+  const int64_t ntile = (int64_t)a.B * a.tiles_x * a.tiles_y;
+  LS_TRACE("conv_bf16", st);
+  // one persistent form per input shape: as many workgroups as fit on the
+  // device at once, each walking tiles tile, tile + grid, ...
+#define LS_PIPE_G(N, CA, CB, UPA, F32A, F32B, W)                                                         \
+  if (nt == N && ca == CA && cb == CB && upa == UPA && f32a == F32A && f32b == F32B) {                  \
+    auto* fn = &k_conv_bf16_pipe<N, CA, CB, UPA, F32A, F32B, W>;                                         \
+    constexpr size_t plds = pipe_lds_bytes(N, CA + CB);                                                  \
+    static_assert(plds <= LDS_MAX, "pipelined tile exceeds LDS");                                       \
+    if (plds > 65536)                                                                                    \
+      LS_HOST_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),                               \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds));         \
+    int per_cu = 0, dev = 0, cus = 0;                                                                    \
+    LS_HOST_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, plds));                \
+    LS_HOST_CHECK(hipGetDevice(&dev));                                                                   \
+    LS_HOST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));             \
+    const int64_t want = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);                                \
+    const dim3 pgrid((unsigned)std::min<int64_t>(want, ntile));                                          \
+    hipLaunchKernelGGL((k_conv_bf16_pipe<N, CA, CB, UPA, F32A, F32B, W>), pgrid, dim3(256), plds, st, a); \
+    LS_LAUNCH_CHECK();                                                                                   \
+    return LS_OK;                                                                                        \
+  }
+  // the shapes of the paper's refinement network (per-input encoders, decoders, final CNN)
+  LS_PIPE_G(4, 8, 0, false, true, false, 1)
+  LS_PIPE_G(2, 16, 0, false, false, false, 2)
+  LS_PIPE_G(2, 32, 0, false, false, false, 2)
+  LS_PIPE_G(2, 32, 0, true, false, false, 2)
+  LS_PIPE_G(1, 32, 0, true, false, false, 2)
+  LS_PIPE_G(1, 16, 0, true, false, false, 2)
+  LS_PIPE_G(2, 32, 8, false, false, true, 2)
+  LS_PIPE_G(1, 32, 0, false, false, false, 2)
+#undef LS_PIPE_G
+  return LS_ENOTIMPL;
 }

@@ -22,3 +22,29 @@ int ls_bf16_prep_dgrad_weights(const uint16_t* w_bf16, uint16_t* packed, hipStre
 int ls_bf16_mask_round(const float* g, const uint16_t* act, uint16_t* out, int64_t n, hipStream_t st);
 int ls_bf16_embed8(const float* g, uint16_t* out, int64_t npix, hipStream_t st);
 int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, float* out, hipStream_t st);
+
+// One 3x3 conv as 16 x 16 output tiles (LDS-staged input patch), the form
+// every persistent BF16 conv launch takes.
+struct ConvTileArgs {
+  ConvSrc src;
+  int B, H, W;           // input plane (zero padding outside)
+  int y0, x0, Ho, Wo;    // output window inside the plane
+  int tiles_x, tiles_y;  // output tiles per image
+  const uint16_t* wp;    // packed weights [Npad][Kpad], k = tap*cin + ci
+  int Kpad;
+  const float* bias;
+  int cout;
+  int relu;
+  uint16_t* out_bf16;    // [B][Ho][Wo][out_stride] at channel out_coff, or null
+  float* out_f32;        // same layout, or null
+  int out_stride, out_coff;
+  uint16_t* pool_out;    // 2 x 2 average pool [B][Ho/2][Wo/2][pool_stride] at pool_coff, or null
+  int pool_stride, pool_coff;
+};
+
+// Persistent pipelined BF16 conv (weights in LDS, next patch prefetched) on
+// any ConvTileArgs whose input shape has a compiled form: nt 16-channel
+// output tiles, part a with ca channels (nearest-upsampled if upa, FP32 if
+// f32a), part b with cb channels (FP32 if f32b).  LS_ENOTIMPL otherwise.
+int ls_bf16_conv_pipe(const ConvTileArgs& a, int nt, int ca, int cb, bool upa, bool f32a, bool f32b,
+                      hipStream_t st);

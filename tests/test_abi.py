@@ -73,6 +73,46 @@ def test_grid_validation(lib):
     rc = lib.ls_splat_points(ctypes.byref(gc), None, None, None, None, 5, None, 1, None, None, None, None)
     assert rc == ls.LS_EINVAL
     assert lib.ls_set_conv_config(99, 0, 0, 0) == ls.LS_ERANGE
+    rc = lib.ls_splat_mean(ctypes.byref(gc), None, None, None, None, 5, None, 1, None, None, None)
+    assert rc == ls.LS_EINVAL
+    rc = lib.ls_resolve_mean(ctypes.byref(gc), None, 2, None, None)
+    assert rc == ls.LS_EINVAL
+    rc = lib.ls_target_loss(None, None, None, 1, ctypes.byref(gc), 2, None, None, None, 0, None)
+    assert rc == ls.LS_ERANGE
+    rc = lib.ls_target_loss(None, None, None, 1, ctypes.byref(gc), ls.LOSS_L1, None, None, None, 0, None)
+    assert rc == ls.LS_EINVAL
+    assert ls.workspace_bytes(ls.OP_LOSS, ls.Grid(), 4) > 0
+    v = ls.View(m=[1.0] * 16, width=0, height=4).c()
+    assert lib.ls_raster_points(ctypes.byref(v), None, None, None, None, 0, None, None, None) == ls.LS_ERANGE
+    v = ls.View(m=[1.0] * 16, width=4, height=4).c()
+    assert lib.ls_raster_points(ctypes.byref(v), None, None, None, None, 3, None, None, None) == ls.LS_EINVAL
+    assert lib.ls_raster_points(None, None, None, None, None, 0, None, None, None) == ls.LS_EINVAL
+    assert lib.ls_raster_resolve(None, 5, None, None) == ls.LS_EINVAL
+    gc = ls.Grid(pad=2).c()  # R = 68, not a multiple of 16
+    assert lib.ls_lsnet_num_params(ctypes.byref(gc)) == -1
+    assert lib.ls_lsnet_refine_tiles(None, 0, None, None, 0, ctypes.byref(gc), None, None, None, 0, None) == \
+        ls.LS_ERANGE
+    gc = ls.Grid().c()
+    assert lib.ls_lsnet_refine_tiles(None, 0, None, None, 2, ctypes.byref(gc), None, None, None, 0, None) == \
+        ls.LS_EINVAL
+    assert lib.ls_lsnet_refine_tiles(None, 3, None, None, 0, ctypes.byref(gc), None, None, None, 0, None) == \
+        ls.LS_ERANGE
+
+
+def test_lsnet_parameter_count(lib):
+    """The library's layer table of the paper's network agrees with the
+    weight generator's (and so with the oracle's) at every padded side."""
+    for res, pad in ((64, 16), (64, 0), (16, 8), (32, 16)):
+        g = ls.Grid(res=res, pad=pad, tile_size=res * 1000)
+        assert ls.lsnet_num_params(g) == synth.pnet_weights(0, R=res + 2 * pad).size
+    assert ls.lsnet_num_params(ls.Grid()) == 2_528_708
+    for prec in (ls.FP32, ls.BF16):
+        a = ls.workspace_bytes(ls.OP_REFINE_LSNET, ls.Grid(), 8, 0, prec)
+        b = ls.workspace_bytes(ls.OP_REFINE_LSNET, ls.Grid(), 4096, 0, prec)
+        assert 0 < a < b
+    # bounded: the batch is taken in chunks
+    assert ls.workspace_bytes(ls.OP_REFINE_LSNET, ls.Grid(), 16384, 0, ls.BF16) == \
+        ls.workspace_bytes(ls.OP_REFINE_LSNET, ls.Grid(), 4096, 0, ls.BF16)
 
 
 def test_python_binding_rejects_cpu_tensors(lib):
