@@ -184,6 +184,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="start with one plain 1 GiB device-to-device copy (reference for HBM counters)")
     ap.add_argument("--splat-points", type=int, default=100_000_000)
+    ap.add_argument("--no-stream", action="store_true", help="skip the 16,384-tile streaming figures")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -356,11 +357,28 @@ def main():
             out["splat"] = bench_splat(args.splat_points, dev)
         except Exception as e:  # secondary figure only
             out["splat"] = {"error": repr(e)}
+        try:
+            out["point_kernels"] = bench_point_kernels(dev, args.splat_points)
+        except Exception as e:  # secondary figure only
+            out["point_kernels"] = {"error": repr(e)}
+        try:
+            out["lsnet"] = bench_lsnet(work, x_out, cz, dev)
+        except Exception as e:  # secondary figure only
+            out["lsnet"] = {"error": repr(e)}
+        try:
+            out["single_tile"] = bench_single_tile(dev)
+        except Exception as e:  # secondary figure only
+            out["single_tile"] = {"error": repr(e)}
         if not args.no_backward:
             try:
                 out["backward"] = bench_training(dev)
             except Exception as e:
                 out["backward"] = {"error": repr(e)}
+        if not args.no_stream:
+            try:
+                out["stream"] = bench_stream(dev)
+            except Exception as e:  # secondary figure only
+                out["stream"] = {"error": repr(e)}
 
     # ---------------------------------------------------------------- CPU baseline (oracle)
     if args.cpu_tiles > 0:
@@ -409,10 +427,10 @@ def bench_splat(n_points: int, dev):
 
 def training_set(dev, dense_per_tile: int = 2_000_000, chunk_tiles: int = 16):
     """256 tiles (16 x 16) with 200-800 sparse points each, reconstructed on
-    the GPU, and their targets: the max-height splat of `dense_per_tile`
-    dense points per tile of the same terrain (no noise), normalised."""
-    from paper_2509_20198_amd import train as T
-
+    the GPU, and two targets from `dense_per_tile` dense points per tile of
+    the same terrain (no noise): the max-height splat (the configured target)
+    and the per-texel mean (the paper's ground truth), both textures in
+    metres / [0, 1]."""
     work = synth.train_tiles(seed=4, device=dev)
     region = work.region
     g = ls.Grid.of(region)
@@ -424,28 +442,31 @@ def training_set(dev, dense_per_tile: int = 2_000_000, chunk_tiles: int = 16):
     slot = torch.full((region.tiles_x * region.tiles_y,), -1, dtype=torch.int32, device=dev)
     slot[torch.from_numpy(ids).to(dev)] = torch.arange(nt, dtype=torch.int32, device=dev)
     keys = torch.zeros((nt, region.res, region.res), dtype=torch.int64, device=dev)
+    acc = torch.zeros((nt, region.res, region.res, 5), dtype=torch.int64, device=dev)
     nd = torch.zeros(1, dtype=torch.int64, device=dev)
     for c in range(0, nt, chunk_tiles):
         d = synth.fullres_points(region, ids[c:c + chunk_tiles], dense_per_tile, seed=1000 + c, noise_sigma_m=0.0,
                                  device=dev, terrain_seed=4)
         ls.splat_points(g, d.x, d.y, d.z, d.rgb_u16(), slot, nt, keys=keys, n_dropped=nd)
+        ls.splat_mean(g, d.x, d.y, d.z, d.rgb_u16(), slot, nt, acc=acc, n_dropped=nd)
         del d
-    tex = torch.zeros((nt, region.res, region.res, 4), dtype=torch.float32, device=dev)
-    ls.resolve_keys(g, keys, tex)
-    r_m = (region.tile_size / 2 + region.pad * region.cell) * region.scale_xy
-    t = T.normalise_target(tex, cz, r_m)
+    tex_max = torch.zeros((nt, region.res, region.res, 4), dtype=torch.float32, device=dev)
+    ls.resolve_keys(g, keys, tex_max)
+    tex_mean = ls.resolve_mean(g, acc)
     torch.cuda.synchronize()
-    return work, g, x, cz, t, int((keys == 0).sum().item())
+    return work, g, x, cz, tex_max, tex_mean, int((keys == 0).sum().item())
 
 
 def bench_training(dev, train_steps: int = 60):
     """Refinement backward on the 256-tile training batch: FP32 and BF16
     forward + backward step times (BF16 also with activation recomputation),
-    and a short AdamW run of the BF16 path from random weights."""
+    and short AdamW runs of the BF16 path from random weights: the configured
+    L1 against max-height targets, and the paper's clipped MSE against mean
+    targets."""
     from paper_2509_20198_amd import train as T
 
     t0 = time.perf_counter()
-    work, g, x, cz, t, empty = training_set(dev)
+    work, g, x, cz, tex_max, tex_mean, empty = training_set(dev)
     log(f"training set ready in {time.perf_counter() - t0:.1f} s")
     nt = x.shape[0]
     w0 = torch.from_numpy(synth.unet_weights(1).astype(np.float32)).to(dev)
@@ -473,26 +494,252 @@ def bench_training(dev, train_steps: int = 60):
 
         ms = Timer().run(step, 5, 2)
         ms_rc = Timer().run(step_recompute, 5, 2)
+        flops = 3 * unet_flops(g.res, g.pad) * nt  # forward + input gradient + weight gradient
         out[name] = {"fwd_bwd_ms": ms, "tiles_per_s": nt / (ms * 1e-3), "fwd_bwd_recompute_ms": ms_rc,
+                     "achieved_TFLOPs": flops / (ms * 1e-3) / 1e12,
+                     "frac_peak": flops / (ms * 1e-3) / 1e12 / (PEAK_BF16_TFLOPS if prec == ls.BF16
+                                                                else PEAK_FP32_TFLOPS),
                      "saved_activation_bytes": int(act.numel()),
                      "autotune": {"ms_default": tune["ms_default"], "ms_tuned": tune["ms_tuned"],
                                   "choice": tune["choice"]}}
         del act, ws
     # training: BF16 convolutions, FP32 weights and optimiser state
-    base = float(T.l1_loss(T.linear_baseline(x, g.pad, g.res), t).item())
-    tr = T.Trainer(w0, g, ls.BF16, save_acts=True, total_steps=train_steps)
-    losses = []
+    for key, kind, tex in (("train_bf16", ls.LOSS_L1, tex_max), ("train_bf16_paper_loss", ls.LOSS_CLIPPED_MSE,
+                                                                 tex_mean)):
+        base = T.loss_value(T.linear_baseline(x, g.pad, g.res), tex, cz, g, kind)
+        tr = T.Trainer(w0, g, ls.BF16, save_acts=True, total_steps=train_steps, loss_kind=kind)
+        losses = []
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(train_steps):
+            losses.append(tr.step(x, tex, cz))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        losses = [float(v.item()) for v in losses]
+        out[key] = {"steps": train_steps, "ms_per_step": dt / train_steps * 1e3,
+                    "tiles_per_s_trained": nt * train_steps / dt, "loss_first": losses[0],
+                    "loss_last": losses[-1], "loss_min": min(losses), "linear_baseline_loss": base,
+                    "loss": "L1 vs max-height targets" if kind == ls.LOSS_L1 else
+                    "NaN-masked clipped MSE vs per-texel mean targets",
+                    "optimizer": "AdamW lr 1e-4 betas (0.9, 0.999) eps 1e-5 wd 1e-2, x0.1 at 1/3 and 2/3"}
+    return out
+
+
+def kernel_ms(fn, names, reps=10, warm=3):
+    """Median per-call milliseconds of the named kernel groups (trace events)."""
+    for _ in range(warm):
+        fn()
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(train_steps):
-        losses.append(tr.step(x, t))
+    ls.trace_enable(True)
+    for _ in range(reps):
+        fn()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t1
-    losses = [float(v.item()) for v in losses]
-    out["train_bf16"] = {"steps": train_steps, "ms_per_step": dt / train_steps * 1e3,
-                         "tiles_per_s_trained": nt * train_steps / dt, "loss_first": losses[0],
-                         "loss_last": losses[-1], "loss_min": min(losses), "linear_baseline_loss": base,
-                         "optimizer": "AdamW lr 1e-4 betas (0.9, 0.999) eps 1e-5 wd 1e-2, x0.1 at 1/3 and 2/3"}
+    rec = ls.trace_records()
+    ls.trace_enable(False)
+    out = {}
+    for n in names:
+        per = {}
+        # group the records of each call: sum per call, then the median over calls
+        ts = [t for name, t in rec if name == n]
+        k = len(ts) // reps if reps else 0
+        if k:
+            sums = sorted(sum(ts[i * k:(i + 1) * k]) for i in range(reps))
+            per = sums[len(sums) // 2]
+        out[n] = per if k else None
+    return out
+
+
+def bench_single_tile(dev):
+    """The single 400-point tile (plain FP32 path): microseconds per stage."""
+    w = synth.single_tile(seed=1, n=400, device=dev)
+    g = ls.Grid.of(w.region)
+    ps = w.points
+    tl = torch.from_numpy(w.tile_list).to(dev)
+    x, cz, st = ls.recon_tiles(g, ps.x, ps.y, ps.z, ps.rgb_u16(), tl)
+    wt = torch.from_numpy(synth.unet_weights(0).astype(np.float32)).to(dev)
+    wb = ls.pack_weights_bf16(wt)
+    ws_r = ls.alloc_workspace(ls.workspace_bytes(ls.OP_RECON, g, 1, ps.n), dev)
+    ws32 = ls.alloc_workspace(ls.workspace_bytes(ls.OP_REFINE, g, 1, 0, ls.FP32), dev)
+    ws16 = ls.alloc_workspace(ls.workspace_bytes(ls.OP_REFINE, g, 1, 0, ls.BF16), dev)
+    tex = torch.empty((1, g.res, g.res, 4), dtype=torch.float32, device=dev)
+    rec = kernel_ms(lambda: ls.recon_tiles(g, ps.x, ps.y, ps.z, ps.rgb_u16(), tl, x_out=x, cz_out=cz, status=st,
+                                           ws=ws_r), ["bin_count", "bin_scan", "bin_scatter", "recon_tile",
+                                                      "recon_all"], reps=50)
+    f32 = Timer().run(lambda: ls.refine_tiles(wt, x, cz, g, ls.FP32, tex_out=tex, want_y=False, ws=ws32), 50, 5)
+    b16 = Timer().run(lambda: ls.refine_tiles(wt, x, cz, g, ls.BF16, w_bf16=wb, tex_out=tex, want_y=False,
+                                              ws=ws16), 50, 5)
+    whole = Timer().run(lambda: (ls.recon_tiles(g, ps.x, ps.y, ps.z, ps.rgb_u16(), tl, x_out=x, cz_out=cz,
+                                                status=st, ws=ws_r),
+                                 ls.refine_tiles(wt, x, cz, g, ls.FP32, tex_out=tex, want_y=False, ws=ws32)), 50, 5)
+    us = lambda v: None if v is None else round(v * 1e3, 1)  # noqa: E731
+    return {"workload": "single_tile_400: one 640 m tile, 400 sparse points, 96 x 96 grid",
+            "us_recon_kernel_groups": {k: us(v) for k, v in rec.items()},
+            "us_refine_fp32": us(f32), "us_refine_bf16": us(b16), "us_recon_plus_fp32_refine": us(whole),
+            "note": "latency-bound (one tile on 256 CUs); the paper's CPU triangulation and sampling take 16 ms "
+                    "per patch and its CNN 4 ms on an RTX 3090 (context only, other hardware)"}
+
+
+def bench_stream(dev, splat_points: int = 500_000_000, splat_tiles: int = 256):
+    """The 16,384-tile streaming case (128 x 128 tiles, Pareto-distributed
+    sparse counts, tiles sorted by distance to a random viewpoint): recon +
+    BF16 refine of the whole set, the time at which the nearest tiles are
+    finished when the list is processed as prioritised sub-batches, and the
+    500 M-point full-resolution splat over the nearest tiles."""
+    work = synth.stream_tiles(seed=5, device=dev)
+    region = work.region
+    g = ls.Grid.of(region)
+    ps = work.points
+    nt = len(work.tile_list)
+    tl = torch.from_numpy(work.tile_list).to(dev)
+    x, y, z, rgb = ps.x.contiguous(), ps.y.contiguous(), ps.z.contiguous(), ps.rgb_u16()
+    w = torch.from_numpy(synth.unet_weights(0).astype(np.float32)).to(dev)
+    wb = ls.pack_weights_bf16(w)
+    R, res = g.R, g.res
+    x_out = torch.empty((nt, R, R, 8), dtype=torch.float32, device=dev)
+    cz = torch.empty(nt, dtype=torch.float64, device=dev)
+    st = torch.empty(nt, dtype=torch.int32, device=dev)
+    tex = torch.empty((nt, res, res, 4), dtype=torch.float32, device=dev)
+    ws_r = ls.alloc_workspace(ls.workspace_bytes(ls.OP_RECON, g, nt, ps.n), dev)
+    ws16 = ls.alloc_workspace(ls.workspace_bytes(ls.OP_REFINE, g, nt, 0, ls.BF16), dev)
+    out = {"workload": f"stream_16384_tiles: 128 x 128 tiles (81.92 km), {ps.n} sparse points (Pareto 20-5000 "
+                       "per tile), tiles sorted by distance to a viewpoint"}
+
+    def whole(order):
+        ls.recon_tiles(g, x, y, z, rgb, tl, order=order, x_out=x_out, cz_out=cz, status=st, ws=ws_r)
+        ls.refine_tiles(w, x_out, cz, g, ls.BF16, w_bf16=wb, tex_out=tex, want_y=False, ws=ws16)
+
+    for key, order in (("whole_longest_first", ls.ORDER_LONGEST_FIRST), ("whole_list_order", ls.ORDER_LIST)):
+        ms = Timer().run(lambda: whole(order), 5, 2)
+        out[key] = {"ms": ms, "tiles_per_s": nt / (ms * 1e-3), "sparse_points_per_s": ps.n / (ms * 1e-3)}
+    stages = kernel_ms(lambda: whole(ls.ORDER_LONGEST_FIRST), ["bin_count", "bin_scan", "bin_scatter", "recon_tile",
+                                                               "conv_bf16"], reps=3, warm=1)
+    out["stage_ms"] = stages
+    if stages.get("recon_tile"):
+        out["recon_hbm_frac"] = nt * R * R * 8 * 4 / (stages["recon_tile"] * 1e-3) / 1e9 / PEAK_HBM_GBS
+    if stages.get("conv_bf16"):
+        out["conv_mfma_frac"] = unet_flops(res, g.pad) * nt / (stages["conv_bf16"] * 1e-3) / 1e12 / PEAK_BF16_TFLOPS
+    # prioritised sub-batches: the nearest 256, the next 768, the rest
+    bounds = [0, 256, 1024, nt]
+    views = []
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        views.append((tl[a:b], x_out[a:b], cz[a:b], st[a:b], tex[a:b]))
+    wss = [(ls.alloc_workspace(ls.workspace_bytes(ls.OP_RECON, g, b - a, ps.n), dev),
+            ls.alloc_workspace(ls.workspace_bytes(ls.OP_REFINE, g, b - a, 0, ls.BF16), dev))
+           for a, b in zip(bounds[:-1], bounds[1:])]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in bounds]
+    times = []
+    for rep in range(4):
+        torch.cuda.synchronize()
+        ev[0].record()
+        for k, ((tlk, xk, czk, stk, texk), (wr, wf)) in enumerate(zip(views, wss)):
+            ls.recon_tiles(g, x, y, z, rgb, tlk, order=ls.ORDER_LIST, x_out=xk, cz_out=czk, status=stk, ws=wr)
+            ls.refine_tiles(w, xk, czk, g, ls.BF16, w_bf16=wb, tex_out=texk, want_y=False, ws=wf)
+            ev[k + 1].record()
+        torch.cuda.synchronize()
+        if rep > 0:
+            times.append([ev[0].elapsed_time(e) for e in ev[1:]])
+    med = np.median(np.asarray(times), 0)
+    out["prioritised_sub_batches"] = {"ms_nearest_256_done": float(med[0]), "ms_nearest_1024_done": float(med[1]),
+                                      "ms_all_done": float(med[2]),
+                                      "how": "recon (tile-list order) + BF16 refine per sub-batch [256, 768, rest] "
+                                             "of the distance-sorted list, events after each"}
+    out["tile_status_nonzero"] = int((st != 0).sum().item())
+    del x_out, ws_r, ws16, wss, views
+    # full-resolution splat over the nearest tiles
+    ids = np.asarray(work.tile_list[:splat_tiles], np.int64)
+    per = splat_points // splat_tiles
+    n = per * splat_tiles
+    bx = torch.empty(n, dtype=torch.int32, device=dev)
+    by, bz = torch.empty_like(bx), torch.empty_like(bx)
+    brgb = torch.empty((n, 3), dtype=torch.int16, device=dev)
+    step = 16
+    for c in range(0, splat_tiles, step):
+        d = synth.fullres_points(region, ids[c:c + step], per, seed=5000 + c, device=dev, terrain_seed=5)
+        a0, a1 = c * per, (c + len(ids[c:c + step])) * per
+        bx[a0:a1], by[a0:a1], bz[a0:a1], brgb[a0:a1] = d.x, d.y, d.z, d.rgb_u16()
+        del d
+    slot = torch.full((region.tiles_x * region.tiles_y,), -1, dtype=torch.int32, device=dev)
+    slot[torch.from_numpy(ids).to(dev)] = torch.arange(splat_tiles, dtype=torch.int32, device=dev)
+    keys = torch.zeros((splat_tiles, res, res), dtype=torch.int64, device=dev)
+    nd = torch.zeros(1, dtype=torch.int64, device=dev)
+    ms = kernel_ms(lambda: ls.splat_points(g, bx, by, bz, brgb, slot, splat_tiles, keys=keys, n_dropped=nd),
+                   ["splat"], reps=5, warm=2)["splat"]
+    alg = n * 18 + splat_tiles * res * res * 8
+    out["splat"] = {"points": n, "tiles": splat_tiles, "ms": ms, "points_per_s": n / (ms * 1e-3),
+                    "algorithmic_GBps": alg / (ms * 1e-3) / 1e9, "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    del bx, by, bz, brgb
+    return out
+
+
+def lsnet_flops(res: int, pad: int) -> float:
+    """Multiply-add FLOPs (x2) of one tile through the paper's network as the
+    library runs it (the first encoder layers as one 8 -> 64 conv, the FC1
+    pair as one GEMM with its zero blocks, the last layer on the crop)."""
+    R = res + 2 * pad
+    L = (R // 16) ** 2 * 32
+    f = 2 * R * R * 64 * 9 * 8
+    f += 4 * 2 * (R // 2) ** 2 * 32 * 9 * 16 + 4 * 2 * (R // 4) ** 2 * 32 * 9 * 32 + 4 * 2 * (R // 8) ** 2 * 32 * 9 * 32
+    f += 2 * 512 * 4 * L + 2 * 2 * L * 512
+    f += 2 * (2 * (R // 8) ** 2 * 32 * 9 * 32 + 2 * (R // 4) ** 2 * 32 * 9 * 32 + 2 * (R // 2) ** 2 * 16 * 9 * 32
+              + 2 * R * R * 16 * 9 * 16)
+    f += 2 * R * R * 32 * 9 * 40 + 2 * R * R * 32 * 9 * 32 + 2 * res * res * 4 * 9 * 32
+    return float(f)
+
+
+def bench_lsnet(work, x_out, cz, dev):
+    """The paper's refinement network on the 1024-tile batch: BF16 and FP32."""
+    g = ls.Grid.of(work.region)
+    nt = x_out.shape[0]
+    w = torch.from_numpy(synth.pnet_weights(0, R=g.R).astype(np.float32)).to(dev)
+    out = {"network": f"the paper's architecture, {ls.lsnet_num_params(g)} parameters"}
+    for name, prec in (("bf16", ls.BF16), ("fp32", ls.FP32)):
+        ws = ls.alloc_workspace(ls.workspace_bytes(ls.OP_REFINE_LSNET, g, nt, 0, prec), dev)
+        tex = torch.empty((nt, g.res, g.res, 4), dtype=torch.float32, device=dev)
+        ms = Timer().run(lambda: ls.lsnet_refine_tiles(w, x_out, cz, g, prec, tex_out=tex, want_y=False, ws=ws),
+                         5 if prec == ls.BF16 else 2, 1)
+        tf = lsnet_flops(g.res, g.pad) * nt / (ms * 1e-3) / 1e12
+        out[name] = {"ms": ms, "tiles_per_s": nt / (ms * 1e-3), "TFLOPs": tf,
+                     "frac_peak": tf / (PEAK_BF16_TFLOPS if prec == ls.BF16 else PEAK_FP32_TFLOPS)}
+        del ws
+    return out
+
+
+def bench_point_kernels(dev, n_points: int = 100_000_000):
+    """Mean splat (ground truth) and point rasteriser on the 100 M-point
+    full-resolution set over 64 x 64 tiles."""
+    region = synth.Region(tiles_x=64, tiles_y=64)
+    g = ls.Grid.of(region)
+    ps = synth.fullres_uniform(region, n_points, seed=3, device=dev)
+    x, y, z = ps.x.contiguous(), ps.y.contiguous(), ps.z.contiguous()
+    rgb = ps.rgb_u16()
+    del ps
+    nslots = 64 * 64
+    ts = torch.arange(nslots, dtype=torch.int32, device=dev)
+    acc = torch.zeros((nslots, 64, 64, 5), dtype=torch.int64, device=dev)
+    nd = torch.zeros(1, dtype=torch.int64, device=dev)
+    ms = kernel_ms(lambda: ls.splat_mean(g, x, y, z, rgb, ts, nslots, acc=acc, n_dropped=nd), ["splat_mean"],
+                   reps=5, warm=2)["splat_mean"]
+    alg = n_points * 18 + nslots * 4096 * 40
+    out = {"splat_mean": {"workload": f"{n_points} points, 64 x 64 tiles, Morton-ordered", "ms": ms,
+                          "points_per_s": n_points / (ms * 1e-3), "algorithmic_GBps": alg / (ms * 1e-3) / 1e9,
+                          "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                          "algorithmic_bytes": "18 B per point + 40 B of sums per texel"}}
+    del acc
+    # a perspective view over the region from 3 km up, 1920 x 1080
+    side = 64 * 640.0
+    f = 1.2
+    M = np.array([[f, 0, 0, -side / 2 * f], [0, f * 16 / 9, 0, -side / 2 * f * 16 / 9], [0, 0, 0, 0],
+                  [0, 0, -1, 3000.0]]) / 20000.0
+    view = ls.View(m=M, width=1920, height=1080)
+    fb = torch.full((1080, 1920), -1, dtype=torch.int64, device=dev)
+    nd = torch.zeros(1, dtype=torch.int64, device=dev)
+    ms = kernel_ms(lambda: ls.raster_points(view, x, y, z, rgb, fb=fb, n_drawn=nd), ["raster"], reps=5,
+                   warm=2)["raster"]
+    drawn = int(nd.item()) // 7
+    alg = n_points * 18 + 1920 * 1080 * 8
+    out["raster"] = {"workload": f"{n_points} points, 1920 x 1080 frame buffer, {drawn} drawn", "ms": ms,
+                     "points_per_s": n_points / (ms * 1e-3), "algorithmic_GBps": alg / (ms * 1e-3) / 1e9,
+                     "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
     return out
 
 

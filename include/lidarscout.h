@@ -42,7 +42,8 @@ extern "C" {
  * paper's 16-texel ring, Section 3.3), covering the window
  * [c - H, c + H) with c the tile centre and H = tile_size/2 + pad*cell.
  * Requirements: tile_size % res == 0, cell even, R % 4 == 0, pad >= 0,
- * 1 <= res, H <= 65535 raw units, |origin_x|, |origin_y| <= 2^40. */
+ * 1 <= res, H <= 262143 raw units (2^18 - 1: with 1 cm units, cells up to
+ * 40 m at res 64 with the 16-texel ring), |origin_x|, |origin_y| <= 2^40. */
 typedef struct ls_grid {
   int64_t origin_x, origin_y;
   int32_t tile_size;
@@ -194,17 +195,40 @@ int ls_refine_tiles(const float* w, const uint16_t* w_bf16, int precision, const
  * Returns the parameter count, or -1 for an invalid grid or R % 16 != 0. */
 int64_t ls_lsnet_num_params(const ls_grid* g);
 
+/* Inputs of the paper's network, as bits of `inputs` (Section 4.3 ablation:
+ * variants that see only some of the reconstructed maps).  An absent input
+ * reads as zero everywhere (its encoder then yields a constant feature
+ * vector, which the FC layers absorb into their biases, and its skip
+ * channels contribute nothing), and an absent linear input also drops out
+ * of the residual: y = f3 + crop(x_lin if present).  HM only = h_lin | h_nn
+ * (its colour output is unused), NN only = h_nn | rgb_nn, Lin only = h_lin |
+ * rgb_lin. */
+typedef enum ls_inputs {
+  LS_IN_HLIN = 1,
+  LS_IN_HNN = 2,
+  LS_IN_RGBLIN = 4,
+  LS_IN_RGBNN = 8,
+  LS_IN_ALL = 15,
+  LS_IN_HM_ONLY = LS_IN_HLIN | LS_IN_HNN,
+  LS_IN_NN_ONLY = LS_IN_HNN | LS_IN_RGBNN,
+  LS_IN_LIN_ONLY = LS_IN_HLIN | LS_IN_RGBLIN
+} ls_inputs;
+
 /* Forward of that network on a batch: same x, cz, y_out, tex_out as
- * ls_refine_tiles.  LS_FP32: FP32 operands and accumulation; LS_BF16: the
+ * ls_refine_tiles; `inputs` selects the inputs the network sees (ls_inputs
+ * bits, LS_IN_ALL for the full network).  LS_FP32: FP32 operands and
+ * accumulation; LS_BF16: the
  * FP32 weights rounded to BF16 (nearest even) inside the call, BF16
  * operands on the matrix cores with FP32 accumulation, every stored hidden
  * activation BF16, the final layer, residual and denormalisation FP32.
  *  ws: ls_workspace_bytes(LS_OP_REFINE_LSNET, g, n_tiles, 0, precision)
  *    bytes (bounded: the batch is processed in chunks).
- * Errors: LS_ERANGE for R % 16 != 0 or another precision; LS_EINVAL for
- * null w or x (n_tiles > 0), or tex_out without cz; LS_EWORKSPACE. */
-int ls_lsnet_refine_tiles(const float* w, int precision, const float* x, const double* cz, int32_t n_tiles,
-                          const ls_grid* g, float* y_out, float* tex_out, void* ws, size_t ws_bytes, void* stream);
+ * Errors: LS_ERANGE for R % 16 != 0, another precision or inputs outside
+ * [1, LS_IN_ALL]; LS_EINVAL for null w or x (n_tiles > 0), or tex_out
+ * without cz; LS_EWORKSPACE. */
+int ls_lsnet_refine_tiles(const float* w, int precision, int32_t inputs, const float* x, const double* cz,
+                          int32_t n_tiles, const ls_grid* g, float* y_out, float* tex_out, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* Refinement network backward, for training the network (Section 3.4,
  * training paragraph: the network is fitted to ground-truth heightmaps with a

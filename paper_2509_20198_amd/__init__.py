@@ -26,6 +26,8 @@ TILE_EMPTY, TILE_NN_ONLY, TILE_CAP, TILE_DEGENERATE, TILE_BADID = 1, 2, 4, 8, 16
 FP32, BF16 = 0, 1
 OP_RECON, OP_REFINE, OP_BACKWARD, OP_SPLAT, OP_LOSS, OP_REFINE_LSNET = 0, 1, 2, 3, 4, 5
 LOSS_CLIPPED_MSE, LOSS_L1 = 0, 1
+IN_HLIN, IN_HNN, IN_RGBLIN, IN_RGBNN, IN_ALL = 1, 2, 4, 8, 15
+IN_HM_ONLY, IN_NN_ONLY, IN_LIN_ONLY = IN_HLIN | IN_HNN, IN_HNN | IN_RGBNN, IN_HLIN | IN_RGBLIN
 ORDER_LIST, ORDER_LONGEST_FIRST = 0, 1
 
 EXPORTS = [
@@ -129,7 +131,7 @@ def load_library(path: str = LIB_PATH):
         lib.ls_lsnet_num_params.restype = i64
         lib.ls_lsnet_num_params.argtypes = [G]
         lib.ls_lsnet_refine_tiles.restype = ctypes.c_int
-        lib.ls_lsnet_refine_tiles.argtypes = [P, ctypes.c_int, P, P, i32, G, P, P, P, sz, P]
+        lib.ls_lsnet_refine_tiles.argtypes = [P, ctypes.c_int, i32, P, P, i32, G, P, P, P, sz, P]
         lib.ls_pack_weights_bf16.restype = ctypes.c_int
         lib.ls_pack_weights_bf16.argtypes = [P, P, P]
         lib.ls_conv_num_configs.restype = ctypes.c_int
@@ -347,9 +349,12 @@ def lsnet_num_params(grid) -> int:
     return n
 
 
-def lsnet_refine_tiles(w, x, cz, grid, precision: int = FP32, *, y_out=None, tex_out=None, want_y: bool = True,
-                       want_tex: bool = True, ws=None, stream=None):
-    """The paper's refinement network forward -> (y [n,res,res,4], tex [n,res,res,4]) (either may be None)."""
+def lsnet_refine_tiles(w, x, cz, grid, precision: int = FP32, *, inputs: int = IN_ALL, y_out=None, tex_out=None,
+                       want_y: bool = True, want_tex: bool = True, ws=None, stream=None):
+    """The paper's refinement network forward -> (y [n,res,res,4], tex [n,res,res,4]) (either may be None).
+
+    inputs: IN_* bits of the maps the network sees (IN_HM_ONLY, IN_NN_ONLY, IN_LIN_ONLY for the
+    ablation variants); absent inputs read as zero."""
     lib = load_library()
     g = Grid.of(grid)
     P = lsnet_num_params(g)
@@ -372,7 +377,7 @@ def lsnet_refine_tiles(w, x, cz, grid, precision: int = FP32, *, y_out=None, tex
         ws = alloc_workspace(need, dev)
     _need(ws, "ws", (torch.uint8,), numel=need)
     gc = g.c()
-    rc = lib.ls_lsnet_refine_tiles(_ptr(w), precision, _ptr(x), _ptr(cz), nt, ctypes.byref(gc), _ptr(y_out),
+    rc = lib.ls_lsnet_refine_tiles(_ptr(w), precision, int(inputs), _ptr(x), _ptr(cz), nt, ctypes.byref(gc), _ptr(y_out),
                                    _ptr(tex_out), _ptr(ws), ws.numel(), _stream(stream))
     _check(rc, "ls_lsnet_refine_tiles")
     return y_out, tex_out

@@ -187,17 +187,20 @@ int64_t ls_lsnet_num_params(const ls_grid* g) {
   return ls_lsnet_params(gi.R);
 }
 
-int ls_lsnet_refine_tiles(const float* w, int precision, const float* x, const double* cz, int32_t n_tiles,
-                          const ls_grid* g, float* y_out, float* tex_out, void* ws, size_t ws_bytes, void* stream) {
+int ls_lsnet_refine_tiles(const float* w, int precision, int32_t inputs, const float* x, const double* cz,
+                          int32_t n_tiles, const ls_grid* g, float* y_out, float* tex_out, void* ws, size_t ws_bytes,
+                          void* stream) {
   LsGridInfo gi;
   const int rc = ls_grid_info(g, &gi);
   if (rc != LS_OK) return rc;
   if (gi.R % 16) return LS_ERANGE;
   if (precision != LS_FP32 && precision != LS_BF16) return LS_ERANGE;
+  if (inputs < 1 || inputs > LS_IN_ALL) return LS_ERANGE;
   if (n_tiles < 0) return LS_EINVAL;
   if (n_tiles > 0 && (!w || !x)) return LS_EINVAL;
   if (tex_out && !cz) return LS_EINVAL;
-  return ls_lsnet_forward_impl(w, precision, x, cz, n_tiles, gi, y_out, tex_out, ws, ws_bytes, ls_stream(stream));
+  return ls_lsnet_forward_impl(w, precision, inputs, x, cz, n_tiles, gi, y_out, tex_out, ws, ws_bytes,
+                               ls_stream(stream));
 }
 
 int ls_refine_backward(const float* w, const uint16_t* w_bf16, int precision, const float* x,

@@ -76,7 +76,9 @@ static inline int ls_grid_info(const ls_grid* g, LsGridInfo* gi) {
   const int64_t R = (int64_t)g->res + 2 * (int64_t)g->pad;
   if (R % 4 || R > 4096) return LS_ERANGE;
   const int64_t H = (int64_t)g->tile_size / 2 + (int64_t)g->pad * C;
-  if (H > 65535) return LS_ERANGE;  // keeps exact predicates in range
+  // tile-local coordinates below 2^18 keep every predicate exact: orientations
+  // below 2^39 in double, in-circle terms below 2^79 in int128
+  if (H > 262143) return LS_ERANGE;
   // origins within 2^40 raw units keep point-to-origin differences exact in double
   const int64_t lim = (int64_t)1 << 40;
   if (g->origin_x < -lim || g->origin_x > lim || g->origin_y < -lim || g->origin_y > lim) return LS_ERANGE;
@@ -147,9 +149,9 @@ int ls_raster_impl(const ls_view& v, const int32_t* x, const int32_t* y, const i
 int ls_raster_resolve_impl(const uint64_t* fb, int64_t n_pixels, uint32_t* rgba, hipStream_t st);
 int64_t ls_lsnet_params(int R);
 size_t ls_lsnet_ws_bytes(const LsGridInfo& gi, int32_t n_tiles, int precision);
-int ls_lsnet_forward_impl(const float* w, int precision, const float* x, const double* cz, int32_t n_tiles,
-                          const LsGridInfo& gi, float* y_out, float* tex_out, void* ws, size_t ws_bytes,
-                          hipStream_t st);
+int ls_lsnet_forward_impl(const float* w, int precision, int inputs, const float* x, const double* cz,
+                          int32_t n_tiles, const LsGridInfo& gi, float* y_out, float* tex_out, void* ws,
+                          size_t ws_bytes, hipStream_t st);
 int ls_zero_f32(float* p, int64_t n, hipStream_t st);
 int ls_conv_num_configs_impl(int layer, int precision, int pass);
 int ls_conv_config_get(int layer, int precision, int pass);

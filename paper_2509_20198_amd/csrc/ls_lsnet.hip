@@ -116,6 +116,7 @@ struct PrepArgs {
   float* f32;
   uint16_t* bf16;
   int L;
+  int inputs;  // bit i: input I_i present (absent inputs are zero)
   int nseg;
   int64_t woff[NL], boff[NL];
   Seg seg[MAX_SEG];
@@ -149,10 +150,21 @@ __device__ __forceinline__ float fc2_value(const PrepArgs& A, int64_t n, int k) 
 // encoder e's input channels.
 __device__ __forceinline__ float enc1_value(const PrepArgs& A, int co, int tap, int ci) {
   const int e = co / 16, j = co % 16;
+  if (!((A.inputs >> e) & 1)) return 0.f;  // an absent input reads as zero
   const int c0 = e == 0 ? 0 : (e == 1 ? 1 : (e == 2 ? 2 : 5));
   const int cn = e < 2 ? 1 : 3;
   if (ci < c0 || ci >= c0 + cn) return 0.f;
   return A.w[A.woff[L_ENC + 4 * e] + ((int64_t)j * 9 + tap) * cn + (ci - c0)];
+}
+
+// Input I_i that x channel ch belongs to: 0 h_lin, 1 h_nn, 2 rgb_lin, 3 rgb_nn.
+__device__ __forceinline__ int input_of_channel(int ch) { return ch == 0 ? 0 : (ch == 1 ? 1 : (ch < 5 ? 2 : 3)); }
+
+// Weight of conv layer `layer` at (co, tap, ci); the final CNN's first
+// layer sees an absent input's skip channels as zero.
+__device__ __forceinline__ float conv_value(const PrepArgs& A, int layer, int cin, int co, int tap, int ci) {
+  if (layer == L_FIN1 && ci >= 32 && !((A.inputs >> input_of_channel(ci - 32)) & 1)) return 0.f;
+  return A.w[A.woff[layer] + ((int64_t)co * 9 + tap) * cin + ci];
 }
 
 __global__ void k_lsnet_prep(PrepArgs A) {
@@ -166,7 +178,7 @@ __global__ void k_lsnet_prep(PrepArgs A) {
       switch (g.kind) {
         case S_CONV_T: {
           const int tap = (int)(r / ((int64_t)cin * cout)), ci = (int)((r / cout) % cin), co = (int)(r % cout);
-          A.f32[g.dst + r] = A.w[A.woff[g.layer] + ((int64_t)co * 9 + tap) * cin + ci];
+          A.f32[g.dst + r] = conv_value(A, g.layer, cin, co, tap, ci);
           break;
         }
         case S_ENC1_T: {
@@ -204,10 +216,7 @@ __global__ void k_lsnet_prep(PrepArgs A) {
         case S_CONV_P: {
           const int n = (int)(r / g.kpad), k = (int)(r % g.kpad);
           float v = 0.f;
-          if (n < cout && k < 9 * cin) {
-            const int tap = k / cin, ci = k % cin;
-            v = A.w[A.woff[g.layer] + ((int64_t)n * 9 + tap) * cin + ci];
-          }
+          if (n < cout && k < 9 * cin) v = conv_value(A, g.layer, cin, n, k / cin, k % cin);
           A.bf16[g.dst + r] = f2bf(v);
           break;
         }
@@ -331,6 +340,31 @@ __global__ void __launch_bounds__(256) k_fc_bf16(const uint16_t* __restrict__ A,
       if (relu) v = fmaxf(v, 0.f);
       C[(int64_t)mm * N + n] = f2bf(v);
     }
+  }
+}
+
+// y = crop(x_lin) + head, with an absent linear input read as zero, and the
+// texture h = cz + r * y_h (double), colour clamped to [0, 1].
+__global__ void k_lsnet_epilogue(const float* __restrict__ head, const float* __restrict__ x,
+                                 const double* __restrict__ cz, int B, int res, int pad, double r_m, int inputs,
+                                 float* __restrict__ y_out, float* __restrict__ tex_out) {
+  const int64_t n = (int64_t)B * res * res;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = (int)(i / ((int64_t)res * res));
+  const int r = (int)(i - (int64_t)b * res * res);
+  const int R = res + 2 * pad;
+  const int yy = r / res + pad, xx = r % res + pad;
+  const float* xp = x + (((int64_t)b * R + yy) * R + xx) * 8;
+  const float4 h = reinterpret_cast<const float4*>(head)[i];
+  const bool lh = inputs & 1, lc = (inputs >> 2) & 1;
+  const float4 v = make_float4((lh ? xp[0] : 0.f) + h.x, (lc ? xp[2] : 0.f) + h.y, (lc ? xp[3] : 0.f) + h.z,
+                               (lc ? xp[4] : 0.f) + h.w);
+  if (y_out) reinterpret_cast<float4*>(y_out)[i] = v;
+  if (tex_out) {
+    const double hm = cz[b] + r_m * (double)v.x;
+    reinterpret_cast<float4*>(tex_out)[i] =
+        make_float4((float)hm, fminf(fmaxf(v.y, 0.f), 1.f), fminf(fmaxf(v.z, 0.f), 1.f), fminf(fmaxf(v.w, 0.f), 1.f));
   }
 }
 
@@ -576,9 +610,9 @@ size_t ls_lsnet_ws_bytes(const LsGridInfo& gi, int32_t n_tiles, int precision) {
   return ws_bytes(gi, n_tiles, precision);
 }
 
-int ls_lsnet_forward_impl(const float* w, int precision, const float* x, const double* cz, int32_t n_tiles,
-                          const LsGridInfo& gi, float* y_out, float* tex_out, void* ws, size_t ws_bytes_given,
-                          hipStream_t st) {
+int ls_lsnet_forward_impl(const float* w, int precision, int inputs, const float* x, const double* cz,
+                          int32_t n_tiles, const LsGridInfo& gi, float* y_out, float* tex_out, void* ws,
+                          size_t ws_bytes_given, hipStream_t st) {
   const int R = gi.R, res = gi.res, pad = gi.pad;
   if (R % 16) return LS_ERANGE;
   if (n_tiles == 0) return LS_OK;
@@ -601,6 +635,7 @@ int ls_lsnet_forward_impl(const float* w, int precision, const float* x, const d
     p.f32 = wf;
     p.bf16 = wb;
     p.L = net.L;
+    p.inputs = inputs;
     p.nseg = d.nseg;
     for (int k = 0; k < NL; ++k) {
       p.woff[k] = net.woff[k];
@@ -723,9 +758,15 @@ int ls_lsnet_forward_impl(const float* w, int precision, const float* x, const d
       LS_TRYN(conv16(src1(part_bf16(F2, 32, R, 32, 0, false)), B, R, wb + d.conv_p[L_FIN3], d.kpad[L_FIN3],
                      w + net.boff[L_FIN3], 4, 0, nullptr, 4, 0, nullptr, 0, 0, head, pad, pad, res, st));
     }
-    LS_TRYN(ls_head_epilogue(head, xc, cz ? cz + t0 : nullptr, B, res, pad, r_m,
-                             y_out ? y_out + (int64_t)t0 * res * res * 4 : nullptr,
-                             tex_out ? tex_out + (int64_t)t0 * res * res * 4 : nullptr, st));
+    {
+      const int64_t ne = (int64_t)B * res * res;
+      LS_TRACE("head_epilogue", st);
+      hipLaunchKernelGGL(k_lsnet_epilogue, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, head, xc,
+                         cz ? cz + t0 : nullptr, B, res, pad, r_m, inputs,
+                         y_out ? y_out + (int64_t)t0 * res * res * 4 : nullptr,
+                         tex_out ? tex_out + (int64_t)t0 * res * res * 4 : nullptr);
+      LS_LAUNCH_CHECK();
+    }
   }
   return LS_OK;
 }

@@ -342,9 +342,10 @@ struct Tile {
   double bw;  // bucket width in raw units
 };
 
-// floor(w * G / W2) for 0 <= w < W2 <= 2^17 and G <= 88 (all products below
-// 2^24): a float reciprocal estimate, off by at most one, then an exact
-// integer correction.
+// floor(w * G / W2) for 0 <= w < W2 <= 2^19 and G <= 88 (all products below
+// 2^26, so the float estimate of a quotient below 88 is off by far less
+// than one): a float reciprocal estimate, then an exact integer correction
+// by at most one.
 __device__ __forceinline__ int bucket_1d(int w, int G, int W2) {
   const int num = w * G;
   int q = (int)((float)num * __builtin_amdgcn_rcpf((float)W2));
@@ -356,13 +357,13 @@ __device__ __forceinline__ int bucket_1d(int w, int G, int W2) {
 }
 
 __device__ __forceinline__ double orient_d(double ax, double ay, double bx, double by, double px, double py) {
-  // exact: |differences| < 2^17, products < 2^34, result < 2^35
+  // exact: |differences| < 2^19, products < 2^38, result < 2^39
   return (bx - ax) * (py - ay) - (by - ay) * (px - ax);
 }
 
 __device__ __forceinline__ int sgn_d(double v) { return (v > 0.0) - (v < 0.0); }
 
-// Exact sign of the in-circle determinant in int128 (|terms| < 2^72), then
+// Exact sign of the in-circle determinant in int128 (|terms| < 2^79), then
 // the symbolic perturbation for exactly cocircular points.  Kept out of line:
 // the floating-point filter below settles nearly every call.
 __device__ __noinline__ int incircle_exact(int a, int b, int c, int d, int2 pa, int2 pb, int2 pc, int2 pd) {
@@ -418,7 +419,7 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
   const int bx0 = bucket_1d(qx + T.H, G, T.W2), by0 = bucket_1d(qy + T.H, G, T.W2);
   const double fx = qx + T.H, fy = qy + T.H;  // grid-local
   int best = -1;
-  double bd = 0.0;  // squared distance, exact in double (below 2^36)
+  double bd = 0.0;  // squared distance, exact in double (below 2^40)
   int bu = 0, bv = 0;
   for (int r = 0;; ++r) {
     const int ylo = by0 - r, yhi = by0 + r, xlo = bx0 - r, xhi = bx0 + r;
@@ -486,7 +487,7 @@ __device__ int nearest_block(const Tile& T, int q0, int C, int R, int bi, int bj
   int by0 = max(bucket_1d(q0 + bi * 8 * C + T.H, G, T.W2) - 1, 0);
   int by1 = min(bucket_1d(q0 + i1 * C + T.H, G, T.W2) + 1, G - 1);
   int best = -1, bu = 0, bv = 0;
-  double bd = 0.0;  // squared distance, exact in double (below 2^36)
+  double bd = 0.0;  // squared distance, exact in double (below 2^40)
   // buckets xlo..xhi of rows ylo..yhi (those of a row are contiguous)
   auto scan = [&](int ylo, int yhi, int xlo, int xhi) {
     if (xlo > xhi) return;

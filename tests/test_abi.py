@@ -52,7 +52,7 @@ def test_host_queries(lib):
 
 def test_grid_validation(lib):
     bad = [ls.Grid(res=63), ls.Grid(pad=15, res=64), ls.Grid(tile_size=64001), ls.Grid(tiles_x=0),
-           ls.Grid(tile_size=200000, pad=16)]
+           ls.Grid(tile_size=600000, pad=16)]
     for g in bad:
         assert ls.workspace_bytes(ls.OP_RECON, g, 1, 1) == 0
     # entry points reject invalid arguments on the host, before touching the GPU
@@ -90,13 +90,16 @@ def test_grid_validation(lib):
     assert lib.ls_raster_resolve(None, 5, None, None) == ls.LS_EINVAL
     gc = ls.Grid(pad=2).c()  # R = 68, not a multiple of 16
     assert lib.ls_lsnet_num_params(ctypes.byref(gc)) == -1
-    assert lib.ls_lsnet_refine_tiles(None, 0, None, None, 0, ctypes.byref(gc), None, None, None, 0, None) == \
+    assert lib.ls_lsnet_refine_tiles(None, 0, 15, None, None, 0, ctypes.byref(gc), None, None, None, 0, None) == \
         ls.LS_ERANGE
     gc = ls.Grid().c()
-    assert lib.ls_lsnet_refine_tiles(None, 0, None, None, 2, ctypes.byref(gc), None, None, None, 0, None) == \
+    assert lib.ls_lsnet_refine_tiles(None, 0, 15, None, None, 2, ctypes.byref(gc), None, None, None, 0, None) == \
         ls.LS_EINVAL
-    assert lib.ls_lsnet_refine_tiles(None, 3, None, None, 0, ctypes.byref(gc), None, None, None, 0, None) == \
+    assert lib.ls_lsnet_refine_tiles(None, 3, 15, None, None, 0, ctypes.byref(gc), None, None, None, 0, None) == \
         ls.LS_ERANGE
+    for bad in (0, 16, -1):
+        assert lib.ls_lsnet_refine_tiles(None, 0, bad, None, None, 0, ctypes.byref(gc), None, None, None, 0,
+                                         None) == ls.LS_ERANGE
 
 
 def test_lsnet_parameter_count(lib):
