@@ -867,13 +867,18 @@ __device__ void raster_hull_edge(const Tile& T, int a, int b, uint64_t key, int 
     for (int j = j0; j <= j1; ++j) fm[i0 * R + j] = key;
     return;
   }
+  // x = ax + dx * (y - ay) / dy must be an integer texel centre; every
+  // quantity is an integer below 2^39, so the double quotient, its rounding
+  // and the check of the product are exact
+  const double fdx = (double)dx, fdy = (double)dy;
   for (int i = i0; i <= i1; ++i) {
-    const int64_t num = dx * (int64_t)(q0 + i * C - ay);
-    if (num % dy) continue;
-    const int64_t x = ax + num / dy;
-    if ((x - q0) % C) continue;
-    const int64_t j = (x - q0) / C;
-    if (j >= j0 && j <= j1) fm[i * R + (int)j] = key;
+    const double num = fdx * (double)(q0 + i * C - ay);
+    const double xr = rint(num / fdy);
+    if (xr * fdy != num) continue;
+    const int xo = ax + (int)xr - q0;
+    if (xo % C) continue;
+    const int j = xo / C;
+    if (j >= j0 && j <= j1) fm[i * R + j] = key;
   }
 }
 

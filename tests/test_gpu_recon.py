@@ -44,7 +44,7 @@ def _compare(region, ps_np, tile_list, gpu=None):
     if "off" in gpu:
         assert np.array_equal(gpu["off"], off)
         assert np.array_equal(gpu["idx"], idx)
-    r = R_M * region.scale_xy / 0.01 if region.pad == 16 else (region.tile_size / 2 + region.pad * region.cell) * region.scale_xy
+    r = (region.tile_size / 2 + region.pad * region.cell) * region.scale_xy  # padded half side, metres
     np.testing.assert_allclose(gpu["cz"], cz, rtol=0, atol=1e-9)
     # heights in metres: linear within 1e-4 m, nearest neighbour exact up to FP32 rounding of x
     err_lin = np.abs(gpu["x"][..., 0] - xo[..., 0]).max() * r
