@@ -739,7 +739,10 @@ def bench_point_kernels(dev, n_points: int = 100_000_000):
     alg = n_points * 18 + 1920 * 1080 * 8
     out["raster"] = {"workload": f"{n_points} points, 1920 x 1080 frame buffer, {drawn} drawn", "ms": ms,
                      "points_per_s": n_points / (ms * 1e-3), "algorithmic_GBps": alg / (ms * 1e-3) / 1e9,
-                     "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+                     "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "traffic": recorded_traffic("ls_raster.hip", "raster_100M_points_traffic.md")
+                     if n_points == 100_000_000 else None,
+                     "traffic_unit": "HBM bytes per launch (counters)"}
     return out
 
 

@@ -68,7 +68,8 @@ struct PointStream {
   const int32_t* y;
   const int32_t* z;
   const uint16_t* rgb;
-  int32_t vec_ok;  // x, y, z 16-byte and rgb 8-byte aligned: quad vector loads
+  int32_t vec_ok;    // x, y, z 16-byte and rgb 8-byte aligned: quad vector loads
+  int32_t vec16_ok;  // also rgb 16-byte aligned: 16-byte colour loads
 };
 
 static inline PointStream point_stream(const int32_t* x, const int32_t* y, const int32_t* z, const uint16_t* rgb,
@@ -81,6 +82,7 @@ static inline PointStream point_stream(const int32_t* x, const int32_t* y, const
   s.z = z;
   s.rgb = rgb;
   s.vec_ok = (al(x, 16) && al(y, 16) && al(z, 16) && al(rgb, 8)) ? 1 : 0;
+  s.vec16_ok = (s.vec_ok && al(rgb, 16)) ? 1 : 0;
   return s;
 }
 
@@ -143,6 +145,59 @@ __device__ __forceinline__ void load_points(const PointStream& p, int64_t base, 
         const int v = 3 * e + ch;  // colour value index within the quad
         r.c[6 * k + v / 2] |= (uint32_t)p.rgb[3 * i + ch] << (16 * (v & 1));
       }
+    }
+  }
+}
+
+// Same fields, but thread t owns the PT_PPT consecutive points base +
+// PT_PPT*t + s (two 16-byte loads per coordinate array, three for the
+// colours): runs of points on one texel stay within a thread, so a kernel
+// can sum them in registers first.  point_colour reads both layouts.
+__device__ __forceinline__ void load_points_consecutive(const PointStream& p, int64_t base, int tid, PointRegs& r) {
+  static_assert(PT_PPT == 8, "two quads per thread");
+  const int64_t first = base + (int64_t)PT_PPT * tid;
+  if (p.vec16_ok && base + PT_BATCH <= p.n) {
+    const int64_t q = first / 4;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const v4i xv = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(p.x) + q + k);
+      const v4i yv = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(p.y) + q + k);
+      const v4i zv = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(p.z) + q + k);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        r.x[4 * k + e] = xv[e];
+        r.y[4 * k + e] = yv[e];
+        r.z[4 * k + e] = zv[e];
+      }
+    }
+    // 8 points x 3 colours x 2 bytes = 48 bytes at a 16-byte aligned offset
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    const v4u* cp = reinterpret_cast<const v4u*>(p.rgb + 3 * first);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const v4u cv = __builtin_nontemporal_load(cp + k);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) r.c[4 * k + e] = cv[e];
+    }
+    r.valid = (1u << PT_PPT) - 1u;
+    return;
+  }
+  r.valid = 0;
+#pragma unroll
+  for (int w = 0; w < PT_PPT * 3 / 2; ++w) r.c[w] = 0;
+#pragma unroll
+  for (int s = 0; s < PT_PPT; ++s) {
+    const int64_t i = first + s;
+    r.x[s] = r.y[s] = r.z[s] = 0;
+    if (i >= p.n) continue;
+    r.valid |= 1u << s;
+    r.x[s] = p.x[i];
+    r.y[s] = p.y[i];
+    r.z[s] = p.z[i];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const int v = 3 * s + ch;
+      r.c[v / 2] |= (uint32_t)p.rgb[3 * i + ch] << (16 * (v & 1));
     }
   }
 }

@@ -4,12 +4,13 @@
 // k_splat_mean: every full-resolution point adds its raw height, its three
 // 16-bit colours and a count of one to its texel.  The sums are integers,
 // so any order gives the same bits.  A workgroup takes a batch of PT_BATCH
-// consecutive points; when their texels fall in a short range of Morton
-// codes (Morton-ordered chunks), the batch is first summed in an LDS window
-// (64-bit height sums, 32-bit colour sums and counts, which cannot overflow
-// within one batch) and flushed with one global 64-bit atomic add per
-// touched texel and field; otherwise every point adds straight to the
-// global sums.
+// consecutive points, each thread PT_PPT consecutive ones, whose runs on one
+// texel (the common case in Morton order) are summed in registers first.
+// When the batch's texels fall in a short range of Morton codes, the runs
+// are then summed in an LDS window (64-bit height sums, 32-bit colour sums
+// and counts, which cannot overflow within one batch) and flushed with one
+// global 64-bit atomic add per touched texel and field; otherwise every run
+// adds straight to the global sums.
 //
 // k_resolve_mean: texel mean = sum / count in double precision (IEEE
 // division), height scaled and offset to metres, colour / 65535; texels
@@ -47,6 +48,12 @@ __device__ __forceinline__ void add_global(unsigned long long* a, long long z, u
   atomicAdd(a + 4, (unsigned long long)cnt);
 }
 
+// Sum of the points of one run (consecutive points of a thread on one texel).
+struct Run {
+  long long z;
+  uint32_t r, g, b, n;
+};
+
 __global__ void __launch_bounds__(PT_THREADS) k_splat_mean(MeanParams p) {
   __shared__ unsigned long long s_z[MEAN_WIN];
   __shared__ uint32_t s_c[MEAN_WIN][4];  // R, G, B sums and count
@@ -64,64 +71,84 @@ __global__ void __launch_bounds__(PT_THREADS) k_splat_mean(MeanParams p) {
   }
   for (int64_t base = (int64_t)blockIdx.x * PT_BATCH; base < p.pts.n; base += (int64_t)gridDim.x * PT_BATCH) {
     PointRegs r;
-    load_points(p.pts, base, tid, r);
-    uint32_t mcs[PT_PPT];
+    load_points_consecutive(p.pts, base, tid, r);
+    // texel key of every point: its Morton code, or its array index when the
+    // grid is too wide for 16-bit Morton halves
+    int64_t key[PT_PPT];
     uint32_t ok = 0;  // bit s: point s lands in a mapped texel
     uint32_t lo = 0xFFFFFFFFu, hi = 0;
 #pragma unroll
     for (int s = 0; s < PT_PPT; ++s) {
-      mcs[s] = 0;
+      key[s] = -1;
       if (!((r.valid >> s) & 1u)) continue;
       int gx, gy;
       if (!point_texel(G, r.x[s], r.y[s], gx, gy)) {
         ++dropped;
         continue;
       }
-      if (!G.morton_ok) {
-        add_global(p.acc + 5 * texel_index(G, gx, gy), r.z[s], point_colour(r, s, 0), point_colour(r, s, 1),
-                   point_colour(r, s, 2), 1u);
-        continue;
-      }
       ok |= 1u << s;
-      const uint32_t mc = spread16((uint32_t)gx) | (spread16((uint32_t)gy) << 1);
-      mcs[s] = mc;
-      lo = min(lo, mc);
-      hi = max(hi, mc);
+      if (G.morton_ok) {
+        const uint32_t mc = spread16((uint32_t)gx) | (spread16((uint32_t)gy) << 1);
+        key[s] = mc;
+        lo = min(lo, mc);
+        hi = max(hi, mc);
+      } else {
+        key[s] = texel_index(G, gx, gy);
+      }
     }
+    bool window = false;
     if (G.morton_ok) {
       block_min_max(lo, hi, s_lo, s_hi, parity);
       parity ^= 1;
-      if (hi >= lo && (hi - lo) < (uint32_t)MEAN_WIN) {
-#pragma unroll
-        for (int s = 0; s < PT_PPT; ++s) {
-          if (!((ok >> s) & 1u)) continue;
-          const uint32_t w = mcs[s] - lo;
-          atomicAdd(&s_z[w], (unsigned long long)(long long)r.z[s]);
-          atomicAdd(&s_c[w][0], point_colour(r, s, 0));
-          atomicAdd(&s_c[w][1], point_colour(r, s, 1));
-          atomicAdd(&s_c[w][2], point_colour(r, s, 2));
-          atomicAdd(&s_c[w][3], 1u);
-        }
-        __syncthreads();
-        const int span = (int)(hi - lo) + 1;
-        for (int w = tid; w < span; w += PT_THREADS) {
-          const uint32_t cnt = s_c[w][3];
-          if (!cnt) continue;
-          const uint32_t code = lo + (uint32_t)w;
-          add_global(p.acc + 5 * texel_index(G, (int)compact16(code), (int)compact16(code >> 1)),
-                     (long long)s_z[w], s_c[w][0], s_c[w][1], s_c[w][2], cnt);
-          s_z[w] = 0;
-          s_c[w][0] = s_c[w][1] = s_c[w][2] = s_c[w][3] = 0;
-        }
-        // the next batch's first barrier (or the kernel's end) orders these
-        // clears before the window is used again
+      window = hi >= lo && (hi - lo) < (uint32_t)MEAN_WIN;  // uniform
+    }
+    // runs of equal keys, summed in registers, then added to the LDS window
+    // or straight to the global sums
+    auto flush = [&](int64_t k, const Run& u) {
+      if (window) {
+        const uint32_t w = (uint32_t)k - lo;
+        atomicAdd(&s_z[w], (unsigned long long)u.z);
+        atomicAdd(&s_c[w][0], u.r);
+        atomicAdd(&s_c[w][1], u.g);
+        atomicAdd(&s_c[w][2], u.b);
+        atomicAdd(&s_c[w][3], u.n);
       } else {
-#pragma unroll
-        for (int s = 0; s < PT_PPT; ++s)
-          if ((ok >> s) & 1u)
-            add_global(p.acc + 5 * texel_index(G, (int)compact16(mcs[s]), (int)compact16(mcs[s] >> 1)), r.z[s],
-                       point_colour(r, s, 0), point_colour(r, s, 1), point_colour(r, s, 2), 1u);
+        const int64_t cell = G.morton_ok ? texel_index(G, (int)compact16((uint32_t)k), (int)compact16((uint32_t)k >> 1))
+                                         : k;
+        add_global(p.acc + 5 * cell, u.z, u.r, u.g, u.b, u.n);
       }
+    };
+    Run u = {0, 0, 0, 0, 0};
+    int64_t cur = -1;
+#pragma unroll
+    for (int s = 0; s < PT_PPT; ++s) {
+      if (!((ok >> s) & 1u)) continue;
+      if (key[s] != cur) {
+        if (u.n) flush(cur, u);
+        cur = key[s];
+        u = Run{0, 0, 0, 0, 0};
+      }
+      u.z += r.z[s];
+      u.r += point_colour(r, s, 0);
+      u.g += point_colour(r, s, 1);
+      u.b += point_colour(r, s, 2);
+      u.n += 1;
+    }
+    if (u.n) flush(cur, u);
+    if (window) {
+      __syncthreads();
+      const int span = (int)(hi - lo) + 1;
+      for (int w = tid; w < span; w += PT_THREADS) {
+        const uint32_t cnt = s_c[w][3];
+        if (!cnt) continue;
+        const uint32_t code = lo + (uint32_t)w;
+        add_global(p.acc + 5 * texel_index(G, (int)compact16(code), (int)compact16(code >> 1)),
+                   (long long)s_z[w], s_c[w][0], s_c[w][1], s_c[w][2], cnt);
+        s_z[w] = 0;
+        s_c[w][0] = s_c[w][1] = s_c[w][2] = s_c[w][3] = 0;
+      }
+      // the next batch's first barrier (or the kernel's end) orders these
+      // clears before the window is used again
     }
   }
   block_count_add(dropped, s_drop, p.n_dropped);
