@@ -586,6 +586,7 @@ int conv16(const ConvSrc& s, int B, int H, const uint16_t* wp, int kpad, const f
   a.pool_out = pool;
   a.pool_stride = pool_stride;
   a.pool_coff = pool_coff;
+  a.mask = nullptr;
   const int nt = (cout + 15) / 16;
   const bool f32b = s.b.c > 0 && s.b.f32 != nullptr;
   return ls_bf16_conv_pipe(a, nt, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr, f32b, st);

@@ -46,6 +46,7 @@ struct RefineWs {
   // BF16 backward: turned weights, masked BF16 gradient, padded head gradient
   uint16_t* wdb;
   uint16_t* gz;
+  uint16_t* gz2;
   uint16_t* gy8;
 };
 
@@ -81,6 +82,7 @@ size_t refine_layout(const LsGridInfo& gi, int32_t B, int precision, int backwar
     if (precision == LS_BF16) {
       W->wdb = A.take<uint16_t>(ls_bf16_dpacked_total());
       W->gz = A.take<uint16_t>(B * 16 * f);
+      W->gz2 = A.take<uint16_t>(B * 16 * f);
       W->gy8 = A.take<uint16_t>((int64_t)B * res * res * 8);
     }
   }
@@ -207,8 +209,12 @@ int wgrad_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* g, int d_s
   a.d_stride = d_stride;
   a.round_in = 1;
   a.partial = partial;
+  // configs 0-2: vector units, 3-5: matrix cores on im2col slabs, 6-8:
+  // matrix cores on 16 x 16 output tiles (up to 32 output channels; the
+  // default where it applies)
   const int cfg = ls_conv_config_get(l, LS_BF16, 2);
-  a.mfma = (cfg < 0 || cfg >= 3) ? 1 : 0;  // default: the matrix cores
+  const bool tile_ok = a.cout <= 32;
+  a.mfma = cfg < 0 ? (tile_ok ? 2 : 1) : (cfg >= 6 ? (tile_ok ? 2 : 1) : (cfg >= 3 ? 1 : 0));
   const int64_t npix = (int64_t)B * Ho * Wo;
   const int chunks = ls_wgrad_chunks_for_config(cfg);
   a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, npix / 256));
@@ -322,25 +328,32 @@ int backward_f32(const float* w, const float* wd, const float* x, const float* a
   return LS_OK;
 }
 
-// BF16 backward: activations saved in BF16, every conv product (dgrad on
-// the matrix cores, wgrad on the vector units) takes BF16 operands with FP32
-// accumulation; gradients between layers stay FP32 and are rounded to BF16
-// (after the ReLU mask) only as conv operands.
+// BF16 backward: activations saved in BF16, every conv product (input and
+// weight gradients on the matrix cores) takes BF16 operands with FP32
+// accumulation.  The gradient at a layer's output is masked by its
+// activation (ReLU') and rounded to BF16 once, as the operand of both
+// products: where the layer above is a plain conv, by the epilogue of that
+// layer's input-gradient conv; where it is a concatenation, an upsampling or
+// a pool, by one pass that also reads the channel slice and adds the pool
+// adjoint.  Gradients between those steps stay FP32.
 int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int B, const LsGridInfo& gi,
                   float* grad_w, float* grad_x, const RefineWs& W, hipStream_t st) {
   const int R = gi.R, R2 = R / 2, R4 = R / 4, res = gi.res, pad = gi.pad;
-  const int64_t f = (int64_t)R * R, h = f / 4, q = f / 16;
+  const int64_t f = (int64_t)R * R;
   const Acts al = act_layout(R);
   auto A = [&](int i) { return acts + al.off[i] * B; };
   auto P = [&](int i, int c, int hw) { return bsrc(A(i), c, hw); };
   const SrcPart X = src_plain(x, 8, R, R, 8, 0, nullptr);
-  // mask + round the gradient of layer l's output, then its wgrad and dgrad
-  auto layer = [&](int l, const float* dA, int act, const ConvSrc& in, int H, float* dX) -> int {
-    const int cout = LS_LAYERS[l].cout;
-    LS_TRY(ls_bf16_mask_round(dA, A(act), W.gz, (int64_t)B * H * H * cout, st));
-    LS_TRY(wgrad_bf16(in, B, H, l, W.gz, cout, 0, 0, H, H, grad_w, W.partial, st));
-    if (!dX) return LS_OK;
-    return ls_bf16_dgrad(one(bsrc(W.gz, cout, H)), B, H, l, W.wdb, dX, st);
+  uint16_t* const g0 = W.gz;
+  uint16_t* const g1 = W.gz2;
+  auto wg = [&](int l, const uint16_t* g, const ConvSrc& in, int H) -> int {
+    return wgrad_bf16(in, B, H, l, g, LS_LAYERS[l].cout, 0, 0, H, H, grad_w, W.partial, st);
+  };
+  // input gradient of layer l from its masked BF16 output gradient g: FP32
+  // into dX, or masked by activation `act_below` into the BF16 buffer gb
+  auto dg = [&](int l, const uint16_t* g, int H, float* dX, int act_below, uint16_t* gb) -> int {
+    return ls_bf16_dgrad(one(bsrc(g, LS_LAYERS[l].cout, H)), B, H, l, W.wdb, dX,
+                         act_below >= 0 ? A(act_below) : nullptr, gb, st);
   };
   // head: gradient embedded at the crop, padded to 8 channels
   LS_TRY(ls_bf16_embed8(grad_y, W.gy8, (int64_t)B * res * res, st));
@@ -348,40 +361,49 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
     SrcPart g = bsrc(W.gy8, 8, res);
     g.oy = pad;
     g.ox = pad;
-    LS_TRY(ls_bf16_dgrad(one(g), B, R, HEAD, W.wdb, W.dXC, st));
+    LS_TRY(ls_bf16_dgrad(one(g), B, R, HEAD, W.wdb, W.dXC, nullptr, nullptr, st));
   }
   LS_TRY(wgrad_bf16(two(P(iA10, 16, R), X), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
-  LS_TRY(ls_copy_channels(W.dXC, 24, 0, W.dA10, 16, B * f, 0, st));
-  // decoder level 1
-  LS_TRY(layer(D1B, W.dA10, iA10, one(P(iA9, 16, R)), R, W.dA9));
+  // decoder level 1: dA10 is the first 16 of the head input's 24 channels
+  LS_TRY(ls_bf16_mask_round_ex(W.dXC, 24, 0, A(iA10), nullptr, B, R, 16, g0, st));
+  LS_TRY(wg(D1B, g0, one(P(iA9, 16, R)), R));
+  LS_TRY(dg(D1B, g0, R, nullptr, iA9, g1));
   SrcPart u8 = P(iA8, 32, R2);
   u8.up = 1;
-  LS_TRY(layer(D1A, W.dA9, iA9, two(u8, P(iA2, 16, R)), R, W.dU1));
+  LS_TRY(wg(D1A, g1, two(u8, P(iA2, 16, R)), R));
+  LS_TRY(dg(D1A, g1, R, W.dU1, -1, nullptr));
   LS_TRY(ls_up_adjoint(W.dU1, 48, W.dA8, B, R2, R2, 32, st));
-  LS_TRY(ls_copy_channels(W.dU1, 48, 32, W.dA2, 16, B * f, 0, st));
   // decoder level 2
-  LS_TRY(layer(D2B, W.dA8, iA8, one(P(iA7, 32, R2)), R2, W.dA7));
+  LS_TRY(ls_bf16_mask_round_ex(W.dA8, 32, 0, A(iA8), nullptr, B, R2, 32, g0, st));
+  LS_TRY(wg(D2B, g0, one(P(iA7, 32, R2)), R2));
+  LS_TRY(dg(D2B, g0, R2, nullptr, iA7, g1));
   SrcPart u6 = P(iA6, 64, R4);
   u6.up = 1;
-  LS_TRY(layer(D2A, W.dA7, iA7, two(u6, P(iA4, 32, R2)), R2, W.dU2));
+  LS_TRY(wg(D2A, g1, two(u6, P(iA4, 32, R2)), R2));
+  LS_TRY(dg(D2A, g1, R2, W.dU2, -1, nullptr));
   LS_TRY(ls_up_adjoint(W.dU2, 96, W.dA6, B, R4, R4, 64, st));
-  LS_TRY(ls_copy_channels(W.dU2, 96, 64, W.dA4, 32, B * h, 0, st));
   // bottleneck
-  LS_TRY(layer(BB, W.dA6, iA6, one(P(iA5, 64, R4)), R4, W.dA5));
-  LS_TRY(layer(BA, W.dA5, iA5, one(P(iP2, 32, R4)), R4, W.dP2));
-  LS_TRY(ls_pool_adjoint_add(W.dP2, W.dA4, B, R2, R2, 32, st));
-  // encoder level 2
-  LS_TRY(layer(E2B, W.dA4, iA4, one(P(iA3, 32, R2)), R2, W.dA3));
-  LS_TRY(layer(E2A, W.dA3, iA3, one(P(iP1, 16, R2)), R2, W.dP1));
-  LS_TRY(ls_pool_adjoint_add(W.dP1, W.dA2, B, R, R, 16, st));
-  // encoder level 1
-  LS_TRY(layer(E1B, W.dA2, iA2, one(P(iA1, 16, R)), R, W.dA1));
-  LS_TRY(layer(E1A, W.dA1, iA1, one(X), R, grad_x));
+  LS_TRY(ls_bf16_mask_round_ex(W.dA6, 64, 0, A(iA6), nullptr, B, R4, 64, g0, st));
+  LS_TRY(wg(BB, g0, one(P(iA5, 64, R4)), R4));
+  LS_TRY(dg(BB, g0, R4, nullptr, iA5, g1));
+  LS_TRY(wg(BA, g1, one(P(iP2, 32, R4)), R4));
+  LS_TRY(dg(BA, g1, R4, W.dP2, -1, nullptr));
+  // encoder level 2: dA4 = skip slice of dU2 + pool adjoint of dP2
+  LS_TRY(ls_bf16_mask_round_ex(W.dU2, 96, 64, A(iA4), W.dP2, B, R2, 32, g0, st));
+  LS_TRY(wg(E2B, g0, one(P(iA3, 32, R2)), R2));
+  LS_TRY(dg(E2B, g0, R2, nullptr, iA3, g1));
+  LS_TRY(wg(E2A, g1, one(P(iP1, 16, R2)), R2));
+  LS_TRY(dg(E2A, g1, R2, W.dP1, -1, nullptr));
+  // encoder level 1: dA2 = skip slice of dU1 + pool adjoint of dP1
+  LS_TRY(ls_bf16_mask_round_ex(W.dU1, 48, 32, A(iA2), W.dP1, B, R, 16, g0, st));
+  LS_TRY(wg(E1B, g0, one(P(iA1, 16, R)), R));
+  LS_TRY(dg(E1B, g0, R, nullptr, iA1, g1));
+  LS_TRY(wg(E1A, g1, one(X), R));
   if (grad_x) {
+    LS_TRY(dg(E1A, g1, R, grad_x, -1, nullptr));
     LS_TRY(ls_copy_channels(W.dXC, 24, 16, grad_x, 8, B * f, 1, st));
     LS_TRY(ls_residual_adjoint(grad_y, grad_x, B, res, pad, st));
   }
-  (void)q;
   return LS_OK;
 }
 

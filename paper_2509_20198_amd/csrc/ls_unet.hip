@@ -471,6 +471,161 @@ __global__ void __launch_bounds__(CT) k_wgrad_mfma(WgradArgs A) {
 // consecutive runs of chunks are summed in parallel (each run in chunk
 // order), then the run sums in run order.  A workgroup covers RED_OUT
 // outputs, so enough workgroups run even for a few thousand outputs.
+// Weight gradient of a 3x3 conv by 16 x 16 output tiles on the matrix cores
+// (BF16 path).  For an output tile the masked BF16 gradient (256 pixels x
+// cout) is staged in LDS transposed, one row of 256 pixels per channel, and
+// the input patch (18 x 18 pixels) of 8 input channels at a time in three
+// copies shifted by the tap's column offset kx = 0, 1, 2 (16 columns each, a
+// row of 16 pixels per channel and patch row).  Every MFMA operand -- 8
+// consecutive pixels of one gradient channel, or of one input channel at
+// one tap -- is then one aligned 16-byte LDS read, and the input is staged
+// once per tile instead of once per tap as the im2col form does.  Columns
+// are enumerated per 8-channel group as 5 tiles of 16 (taps 2t and 2t + 1 x
+// 8 channels; tap 9 is zero padding), and the first column chunk also owns a
+// bias tile (a column of ones).  A workgroup takes the groups of one column
+// chunk (WT_GROUPS groups) for the spatial tiles x, x + gridDim.x, ...;
+// wave w multiplies pixel rows 4w .. 4w + 3 of each tile (two K steps of 32
+// pixels), and the four waves' sums are added in LDS in a fixed order at
+// the end, so the partial sums are deterministic.
+constexpr int WT_GROUPS = 2;            // 8-channel input groups per workgroup
+constexpr int WT_PITCH = 256 + 8;       // staged gradient row: 256 pixels + pad (BF16)
+constexpr int WT_TILES = 5 * WT_GROUPS + 1;  // column tiles per workgroup (+ bias)
+
+template <int MT>
+__global__ void __launch_bounds__(CT) k_wgrad_tile(WgradArgs A) {
+  static_assert(MT * WT_TILES * 64 * 4 * 4 <= WT_GROUPS * 3 * 8 * 18 * 16 * 2, "reduction fits the patch LDS");
+  __shared__ __align__(16) uint16_t s_g[MT * 16][WT_PITCH];
+  __shared__ __align__(16) uint16_t s_x[WT_GROUPS][3][8][18][16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int cin = A.src.a.c + A.src.b.c;
+  const int N = 9 * cin;
+  const int ng8 = cin / 8;
+  const int gbase = blockIdx.y * WT_GROUPS;
+  const int ngr = min(WT_GROUPS, ng8 - gbase);
+  const bool bias = blockIdx.y == 0;
+  const int tiles_x = (A.Wo + 15) / 16, tiles_y = (A.Ho + 15) / 16;
+  const int per_img = tiles_x * tiles_y, ntiles = A.B * per_img;
+  wm_f32x4 acc[MT][WT_TILES];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int t = 0; t < WT_TILES; ++t) acc[mt][t] = wm_f32x4{0.f, 0.f, 0.f, 0.f};
+  wm_u16x8 ones;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) ones[j] = 0x3F80u;  // BF16 1.0
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int b = tile / per_img, tt = tile - b * per_img;
+    const int ty0 = (tt / tiles_x) * 16, tx0 = (tt % tiles_x) * 16;
+    // gradient, transposed: thread = (pixel pair of a row, 4 channels)
+    for (int e = tid; e < 128 * MT * 4; e += CT) {
+      const int pp = e & 127, cq = e >> 7;
+      const int r = pp >> 3, c = 2 * (pp & 7);
+      uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
+      const int oy = ty0 + r, ox = tx0 + c;
+      if (4 * cq < A.cout && oy < A.Ho) {
+        const int64_t o = (((int64_t)b * A.Ho + oy) * A.Wo + ox) * A.d_stride + 4 * cq;
+        if (ox < A.Wo) v0 = *reinterpret_cast<const uint2*>(A.g_bf16 + o);
+        if (ox + 1 < A.Wo) v1 = *reinterpret_cast<const uint2*>(A.g_bf16 + o + A.d_stride);
+      }
+      uint32_t* row = reinterpret_cast<uint32_t*>(&s_g[4 * cq][r * 16 + c]);
+      row[0 * WT_PITCH / 2] = (v0.x & 0xFFFFu) | (v1.x << 16);
+      row[1 * WT_PITCH / 2] = (v0.x >> 16) | (v1.x & 0xFFFF0000u);
+      row[2 * WT_PITCH / 2] = (v0.y & 0xFFFFu) | (v1.y << 16);
+      row[3 * WT_PITCH / 2] = (v0.y >> 16) | (v1.y & 0xFFFF0000u);
+    }
+    // input patch of each group in its three shifted copies
+    for (int e = tid; e < ngr * 18 * 18; e += CT) {
+      const int gi = e / 324, pix = e - gi * 324;
+      const int pr = pix / 18, pc = pix - pr * 18;
+      const int g8 = gbase + gi;
+      const bool in_a = 8 * g8 < A.src.a.c;
+      const uint4 v = wm_load8(in_a ? A.src.a : A.src.b, b, A.y0 + ty0 + pr - 1, A.x0 + tx0 + pc - 1,
+                               in_a ? 8 * g8 : 8 * g8 - A.src.a.c, A.H, A.W);
+      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int kx = 0; kx < 3; ++kx) {
+        const int col = pc - kx;
+        if (col < 0 || col >= 16) continue;
+#pragma unroll
+        for (int ci = 0; ci < 8; ++ci)
+          s_x[gi][kx][ci][pr][col] = (uint16_t)((ci & 1) ? (w4[ci >> 1] >> 16) : (w4[ci >> 1] & 0xFFFFu));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int kstep = 2 * wave + ks;  // pixel rows 2 kstep, 2 kstep + 1
+      wm_bf16x8 af[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+        af[mt] = __builtin_bit_cast(wm_bf16x8, *reinterpret_cast<const wm_u16x8*>(&s_g[mt * 16 + r16][kstep * 32 + 8 * g]));
+      if (bias) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt][WT_TILES - 1] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], __builtin_bit_cast(wm_bf16x8, ones), acc[mt][WT_TILES - 1], 0, 0, 0);
+      }
+      const int orow = 2 * kstep + (g >> 1), ocol = 8 * (g & 1), ci = r16 & 7;
+#pragma unroll
+      for (int gi = 0; gi < WT_GROUPS; ++gi) {
+        if (gi >= ngr) break;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          const int tap = 2 * t + (r16 >> 3);
+          wm_u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
+          if (tap < 9) {
+            const int ky = tap / 3, kx = tap - 3 * ky;
+            bv = *reinterpret_cast<const wm_u16x8*>(&s_x[gi][kx][ci][orow + ky][ocol]);
+          }
+          const wm_bf16x8 bf = __builtin_bit_cast(wm_bf16x8, bv);
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[mt][gi * 5 + t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mt], bf, acc[mt][gi * 5 + t], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // every wave is done with the staged tile
+  }
+  // the four waves' sums in a fixed order, through the patch LDS
+  float* red = reinterpret_cast<float*>(&s_x[0][0][0][0][0]);
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int t = 0; t < WT_TILES; ++t) {
+          float* q = red + (((mt * WT_TILES + t) * 64) + lane) * 4;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) q[i] = (w == 0 ? 0.f : q[i]) + acc[mt][t][i];
+        }
+    }
+    __syncthreads();
+  }
+  // partial sums of this workgroup's pixels: D[co][n], rows co = mt*16 + 4g + i
+  float* out = A.partial + (int64_t)blockIdx.x * ((int64_t)A.cout * N + A.cout);
+  for (int e = tid; e < MT * WT_TILES * 64; e += CT) {
+    const int l = e & 63, mtt = e >> 6;
+    const int mt = mtt / WT_TILES, t = mtt - mt * WT_TILES;
+    const int lr16 = l & 15, lg = l >> 4;
+    const float* q = red + (size_t)e * 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = mt * 16 + 4 * lg + i;
+      if (co >= A.cout) continue;
+      if (t == WT_TILES - 1) {
+        if (bias && lr16 == 0) out[(int64_t)A.cout * N + co] = q[i];
+        continue;
+      }
+      const int gi = t / 5, tp = t - 5 * gi;
+      const int tap = 2 * tp + (lr16 >> 3);
+      if (gi >= ngr || tap >= 9) continue;
+      const int n = tap * cin + 8 * (gbase + gi) + (lr16 & 7);
+      out[(int64_t)co * N + n] = q[i];
+    }
+  }
+}
+
 constexpr int RED_OUT = 16, RED_SEG = CT / RED_OUT;
 __global__ void __launch_bounds__(CT) k_reduce_partials(const float* __restrict__ partial, int nchunk, int64_t n,
                                                       float* __restrict__ out) {
@@ -629,8 +784,16 @@ int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st) {
   const int mwg = a.cout <= 16 ? 16 : (a.cout <= 32 ? 32 : 64);
   if (a.cout > 64) return LS_ENOTIMPL;
   LS_TRACE("wgrad", st);
-  // the matrix-core kernel stages 8 channels of one part at a time
-  if (a.mfma && a.g_bf16 && a.src.a.c % 8 == 0 && a.src.b.c % 8 == 0) {
+  // the tile kernel: 16 x 16 output tiles, the input staged once per tile
+  if (a.mfma == 2 && a.g_bf16 && a.src.a.c % 8 == 0 && a.src.b.c % 8 == 0 && a.cout <= 32 && a.d_stride % 4 == 0) {
+    const int ng8 = cin / 8;
+    dim3 grid((unsigned)a.nchunk, (unsigned)((ng8 + WT_GROUPS - 1) / WT_GROUPS));
+    if (a.cout <= 16)
+      hipLaunchKernelGGL(k_wgrad_tile<1>, grid, dim3(CT), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_wgrad_tile<2>, grid, dim3(CT), 0, st, a);
+  } else if (a.mfma && a.g_bf16 && a.src.a.c % 8 == 0 && a.src.b.c % 8 == 0) {
+    // the matrix-core kernel stages 8 channels of one part at a time
     // column tiles per wave: the fewest that cover the columns in one
     // workgroup, at most 8 (more workgroups along x beyond that)
     const int tiles = (9 * cin + 1 + 15) / 16;
@@ -662,6 +825,7 @@ int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st) {
 }
 
 int ls_up_adjoint(const float* dhigh, int stride, float* dlow, int B, int h, int w, int c_low, hipStream_t st) {
+  LS_TRACE("up_adjoint", st);
   const int64_t n = (int64_t)B * h * w * c_low;
   hipLaunchKernelGGL(k_up_adjoint, dim3(nblk(n)), dim3(CT), 0, st, dhigh, stride, dlow, B, h, w, c_low);
   LS_LAUNCH_CHECK();
@@ -669,12 +833,14 @@ int ls_up_adjoint(const float* dhigh, int stride, float* dlow, int B, int h, int
 }
 
 int ls_copy_channels(const float* src, int stride, int coff, float* dst, int C, int64_t npix, int acc, hipStream_t st) {
+  LS_TRACE("copy_channels", st);
   hipLaunchKernelGGL(k_copy_channels, dim3(nblk(npix * C)), dim3(CT), 0, st, src, stride, coff, dst, C, npix, acc);
   LS_LAUNCH_CHECK();
   return LS_OK;
 }
 
 int ls_pool_adjoint_add(const float* dlow, float* dhigh, int B, int H, int W, int C, hipStream_t st) {
+  LS_TRACE("pool_adjoint", st);
   const int64_t n = (int64_t)B * H * W * C;
   hipLaunchKernelGGL(k_pool_adjoint_add, dim3(nblk(n)), dim3(CT), 0, st, dlow, dhigh, B, H, W, C);
   LS_LAUNCH_CHECK();
@@ -682,6 +848,7 @@ int ls_pool_adjoint_add(const float* dlow, float* dhigh, int B, int H, int W, in
 }
 
 int ls_residual_adjoint(const float* dy, float* dx, int B, int res, int pad, hipStream_t st) {
+  LS_TRACE("residual_adjoint", st);
   const int64_t n = (int64_t)B * res * res;
   hipLaunchKernelGGL(k_residual_adjoint, dim3(nblk(n)), dim3(CT), 0, st, dy, dx, B, res, pad);
   LS_LAUNCH_CHECK();

@@ -46,7 +46,7 @@ struct WgradArgs {
   int round_in;             // round FP32-stored inputs to BF16 (BF16 path)
   float* partial;           // [nchunk][cout*9*cin + cout]
   int nchunk;
-  int mfma;                 // BF16 gradient only: the matrix-core kernel
+  int mfma;                 // BF16 gradient only: 1 the matrix-core im2col kernel, 2 the tile kernel
 };
 
 // Tiling choices per (layer, precision, pass), set by ls_set_conv_config.

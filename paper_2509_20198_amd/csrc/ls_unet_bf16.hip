@@ -34,6 +34,7 @@ struct ConvArgsB {
   uint16_t* out_bf16;  // [B][Ho][Wo][out_stride] or null
   float* out_f32;
   int out_stride;
+  const uint16_t* mask;  // BF16 output: zero where this activation (same layout) is not positive, or null
 };
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
@@ -153,6 +154,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_conv_bf16(ConvArgsB A) {
         if (p >= npix) continue;
         float v = acc[mt][nt][r] + bias;
         if (A.relu) v = fmaxf(v, 0.f);
+        if (A.mask && !(bf2f(A.mask[p * A.out_stride + co]) > 0.f)) v = 0.f;
         if (A.out_bf16) A.out_bf16[p * A.out_stride + co] = f2bf(v);
         else A.out_f32[p * A.out_stride + co] = v;
       }
@@ -392,6 +394,20 @@ __device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f
         if (full || (oy0 + mt < A.Ho && ox < A.Wo))
           *reinterpret_cast<float4*>(A.out_f32 + off0 + mt * row) = make_float4(q[mt][0], q[mt][1], q[mt][2], q[mt][3]);
       continue;
+    }
+    if (A.mask) {
+      // the backward's ReLU' of the layer below, 4 channels of each pixel
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+        if (full || (oy0 + mt < A.Ho && ox < A.Wo)) {
+          const uint2 mv = *reinterpret_cast<const uint2*>(A.mask + off0 + mt * row);
+          const uint32_t mw[2] = {mv.x, mv.y};
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const unsigned short m = (unsigned short)((r & 1) ? (mw[r >> 1] >> 16) : (mw[r >> 1] & 0xFFFFu));
+            if (!(bf2f(m) > 0.f)) q[mt][r] = 0.f;
+          }
+        }
     }
     unsigned short h[4][4];
 #pragma unroll
@@ -710,6 +726,40 @@ __global__ void k_mask_round_bf16(const float* __restrict__ g, const uint16_t* _
   if (i < n) out[i] = f2bf(bf2f(act[i]) > 0.f ? g[i] : 0.f);
 }
 
+// out[p][c] = BF16(g where act[p][c] > 0, else 0) for C channels per
+// pixel, 8 per thread, with g = src[p][coff + c] of a `stride`-channel
+// tensor, plus (low given) the 2x2 average-pool adjoint 0.25 * low[p / 2][c]
+// of a half-resolution gradient: the channel split, the pool adjoint and the
+// masking of the backward in one pass.
+__global__ void k_mask_round_ex(const float* __restrict__ src, int stride, int coff, const uint16_t* __restrict__ act,
+                                const float* __restrict__ low, int B, int H, int W, int C, uint16_t* __restrict__ out) {
+  const int c8n = C / 8;
+  const int64_t n = (int64_t)B * H * W * c8n;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int c0 = 8 * (int)(i % c8n);
+  const int64_t p = i / c8n;
+  const float* sp = src + p * stride + coff + c0;
+  const float4 a0 = *reinterpret_cast<const float4*>(sp), a1 = *reinterpret_cast<const float4*>(sp + 4);
+  float g[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+  if (low) {
+    const int x = (int)(p % W);
+    const int64_t r = p / W;
+    const int y = (int)(r % H);
+    const int b = (int)(r / H);
+    const float* lp = low + (((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c0;
+    const float4 l0 = *reinterpret_cast<const float4*>(lp), l1 = *reinterpret_cast<const float4*>(lp + 4);
+    const float lv[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g[k] += 0.25f * lv[k];
+  }
+  const u16x8 av = *reinterpret_cast<const u16x8*>(act + p * C + c0);
+  u16x8 o;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) o[k] = f2bf(bf2f(av[k]) > 0.f ? g[k] : 0.f);
+  *reinterpret_cast<u16x8*>(out + p * C + c0) = o;
+}
+
 // [npix][4] FP32 -> [npix][8] BF16 with channels 4..7 zero
 __global__ void k_embed8_bf16(const float* __restrict__ g, uint16_t* __restrict__ out, int64_t npix) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -736,12 +786,25 @@ int ls_bf16_prep_dgrad_weights(const uint16_t* w_bf16, uint16_t* packed, hipStre
 }
 
 int ls_bf16_mask_round(const float* g, const uint16_t* act, uint16_t* out, int64_t n, hipStream_t st) {
+  LS_TRACE("mask_round", st);
   hipLaunchKernelGGL(k_mask_round_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, act, out, n);
   LS_LAUNCH_CHECK();
   return LS_OK;
 }
 
+int ls_bf16_mask_round_ex(const float* src, int stride, int coff, const uint16_t* act, const float* low, int B,
+                          int H, int C, uint16_t* out, hipStream_t st) {
+  if (C % 8 || stride % 4 || coff % 4) return LS_ENOTIMPL;
+  LS_TRACE("mask_round", st);
+  const int64_t n = (int64_t)B * H * H * (C / 8);
+  hipLaunchKernelGGL(k_mask_round_ex, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, stride, coff, act, low,
+                     B, H, H, C, out);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
 int ls_bf16_embed8(const float* g, uint16_t* out, int64_t npix, hipStream_t st) {
+  LS_TRACE("embed8", st);
   hipLaunchKernelGGL(k_embed8_bf16, dim3((unsigned)((npix * 8 + 255) / 256)), dim3(256), 0, st, g, out, npix);
   LS_LAUNCH_CHECK();
   return LS_OK;
@@ -750,9 +813,42 @@ int ls_bf16_embed8(const float* g, uint16_t* out, int64_t npix, hipStream_t st) 
 // Input gradient of layer l over the whole H x H plane: the conv of the
 // (masked, BF16) output gradient `s` with the turned weights, FP32 result
 // [B][H][H][cin].
-int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked, float* out, hipStream_t st) {
+int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked, float* out, const uint16_t* mask,
+                  uint16_t* out_masked, hipStream_t st) {
   const int cin = LS_LAYERS[l].cin;
   if (s.a.c + s.b.c != dgrad_cg(l)) return LS_EINVAL;
+  // config 0 / 1: direct operand fetch with 4 / 2 pixel tiles per wave;
+  // 2 and the default: the persistent LDS-tiled form
+  const int cfg = ls_conv_config_get(l, LS_BF16, 1);
+  if (cfg < 0 || cfg == 2) {
+    ConvTileArgs a;
+    a.src = s;
+    a.B = B;
+    a.H = H;
+    a.W = H;
+    a.y0 = 0;
+    a.x0 = 0;
+    a.Ho = H;
+    a.Wo = H;
+    a.tiles_x = (H + TT - 1) / TT;
+    a.tiles_y = (H + TT - 1) / TT;
+    a.wp = dpacked + ls_bf16_dpacked_offset(l);
+    a.Kpad = dgrad_kpad(l);
+    a.bias = nullptr;
+    a.cout = cin;
+    a.relu = 0;
+    a.out_bf16 = mask ? out_masked : nullptr;
+    a.out_f32 = mask ? nullptr : out;
+    a.out_stride = cin;
+    a.out_coff = 0;
+    a.pool_out = nullptr;
+    a.pool_stride = 0;
+    a.pool_coff = 0;
+    a.mask = mask;
+    const int rc = ls_bf16_conv_pipe(a, (cin + 15) / 16, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr,
+                                     s.b.c > 0 && s.b.f32 != nullptr, st, "dgrad_bf16");
+    if (rc != LS_ENOTIMPL) return rc;
+  }
   ConvArgsB a;
   a.src = s;
   a.B = B;
@@ -767,12 +863,14 @@ int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked
   a.bias = nullptr;
   a.cout = cin;
   a.relu = 0;
-  a.out_bf16 = nullptr;
-  a.out_f32 = out;
+  // FP32 input gradient, or (mask given) the BF16 operand of the next layer
+  // down: the gradient zeroed where that layer's activation is not positive
+  a.out_bf16 = mask ? out_masked : nullptr;
+  a.out_f32 = mask ? nullptr : out;
   a.out_stride = cin;
+  a.mask = mask;
   LS_TRACE("dgrad_bf16", st);
-  // config 0: 4 pixel tiles per wave, 1: 2
-  const int mt = ls_conv_config_get(l, LS_BF16, 1) == 1 ? 2 : 4;
+  const int mt = cfg == 1 ? 2 : 4;
   return launch_direct(a, (cin + 15) / 16, mt, (int64_t)B * H * H, st);
 }
 
@@ -850,6 +948,7 @@ int conv_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* packed, con
   a.out_bf16 = out_bf16;
   a.out_f32 = out_f32;
   a.out_stride = a.cout;
+  a.mask = nullptr;
   const int nt = (a.cout + 15) / 16;
   LS_TRACE("conv_bf16", st);
   return launch_direct(a, nt, mt, (int64_t)B * Ho * Wo, st);
@@ -881,6 +980,7 @@ int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed,
   a.out_coff = 0;
   a.pool_stride = a.cout;
   a.pool_coff = 0;
+  a.mask = nullptr;
   if (pool_out && (Ho % TT || Wo % TT)) return LS_ENOTIMPL;
   const int cin = s.a.c + s.b.c;
   const size_t patch = (size_t)PT * PT * patch_pitch(cin) * 2;
@@ -1066,10 +1166,10 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
 }
 
 int ls_bf16_conv_pipe(const ConvTileArgs& a, int nt, int ca, int cb, bool upa, bool f32a, bool f32b,
-                      hipStream_t st) {
+                      hipStream_t st, const char* trace) {
   if (a.B <= 0 || a.tiles_x <= 0 || a.tiles_y <= 0) return LS_OK;
   const int64_t ntile = (int64_t)a.B * a.tiles_x * a.tiles_y;
-  LS_TRACE("conv_bf16", st);
+  LS_TRACE(trace, st);
   // one persistent form per input shape: as many workgroups as fit on the
   // device at once, each walking tiles tile, tile + grid, ...
 #define LS_PIPE_G(N, CA, CB, UPA, F32A, F32B, W)                                                         \
@@ -1099,6 +1199,13 @@ int ls_bf16_conv_pipe(const ConvTileArgs& a, int nt, int ca, int cb, bool upa, b
   LS_PIPE_G(1, 16, 0, true, false, false, 2)
   LS_PIPE_G(2, 32, 8, false, false, true, 2)
   LS_PIPE_G(1, 32, 0, false, false, false, 2)
+  // the input gradients of the U-Net (gradient channels -> layer input channels)
+  LS_PIPE_G(2, 8, 0, false, false, false, 2)
+  LS_PIPE_G(1, 16, 0, false, false, false, 2)
+  LS_PIPE_G(3, 16, 0, false, false, false, 2)
+  LS_PIPE_G(6, 32, 0, false, false, false, 1)
+  LS_PIPE_G(4, 64, 0, false, false, false, 1)
+  LS_PIPE_G(2, 64, 0, false, false, false, 1)
 #undef LS_PIPE_G
   return LS_ENOTIMPL;
 }

@@ -21,7 +21,11 @@ size_t ls_bf16_dpacked_total();
 int ls_bf16_prep_dgrad_weights(const uint16_t* w_bf16, uint16_t* packed, hipStream_t st);
 int ls_bf16_mask_round(const float* g, const uint16_t* act, uint16_t* out, int64_t n, hipStream_t st);
 int ls_bf16_embed8(const float* g, uint16_t* out, int64_t npix, hipStream_t st);
-int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, float* out, hipStream_t st);
+// mask given: instead of FP32 `out`, write out_masked = BF16(dX where mask > 0, else 0)
+int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, float* out, const uint16_t* mask,
+                  uint16_t* out_masked, hipStream_t st);
+int ls_bf16_mask_round_ex(const float* src, int stride, int coff, const uint16_t* act, const float* low, int B, int H,
+                          int C, uint16_t* out, hipStream_t st);
 
 // One 3x3 conv as 16 x 16 output tiles (LDS-staged input patch), the form
 // every persistent BF16 conv launch takes.
@@ -40,6 +44,7 @@ struct ConvTileArgs {
   int out_stride, out_coff;
   uint16_t* pool_out;    // 2 x 2 average pool [B][Ho/2][Wo/2][pool_stride] at pool_coff, or null
   int pool_stride, pool_coff;
+  const uint16_t* mask;  // BF16 output: zero where this activation (output layout) is not positive, or null
 };
 
 // Persistent pipelined BF16 conv (weights in LDS, next patch prefetched) on
@@ -47,4 +52,4 @@ struct ConvTileArgs {
 // output tiles, part a with ca channels (nearest-upsampled if upa, FP32 if
 // f32a), part b with cb channels (FP32 if f32b).  LS_ENOTIMPL otherwise.
 int ls_bf16_conv_pipe(const ConvTileArgs& a, int nt, int ca, int cb, bool upa, bool f32a, bool f32b,
-                      hipStream_t st);
+                      hipStream_t st, const char* trace = "conv_bf16");
