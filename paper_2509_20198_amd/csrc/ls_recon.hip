@@ -335,9 +335,30 @@ struct ReconParams {
   int32_t* status;
 };
 
-struct Tile {
-  const int2* uv;       // canonical coordinates (LDS when the tile fits, else global)
-  const int32_t* boff;  // LDS, G*G + 1 canonical bucket offsets
+// Pointers into LDS typed as such, so that reads through them are LDS reads
+// (a generic pointer that may point to LDS or to global memory compiles to
+// flat loads, which wait on both the LDS and the vector-memory counters).
+typedef const __attribute__((address_space(3))) int32_t* LdsI32;
+typedef const __attribute__((address_space(3))) uint64_t* LdsU64;
+// Point coordinates (u, v) as one 8-byte read, from LDS or global memory.
+struct UvLds {
+  LdsU64 p;
+  __device__ __forceinline__ int2 operator[](int i) const {
+    const uint64_t w = p[i];
+    return make_int2((int)(uint32_t)w, (int)(uint32_t)(w >> 32));
+  }
+};
+struct UvGlobal {
+  const int2* p;
+  __device__ __forceinline__ int2 operator[](int i) const { return p[i]; }
+};
+
+// A tile's canonical points: coordinates through UVP (UvLds when the
+// tile's points are staged in LDS, else UvGlobal).
+template <class UVP>
+struct TileT {
+  UVP uv;       // canonical coordinates
+  LdsI32 boff;  // G*G + 1 canonical bucket offsets
   int G, H, W2;
   double bw;  // bucket width in raw units
 };
@@ -405,7 +426,8 @@ __device__ __forceinline__ int incircle_sos(int a, int b, int c, int d, int2 pa,
   return incircle_exact(a, b, c, d, pa, pb, pc, pd);
 }
 
-__device__ __forceinline__ bool ring_covers_grid(const Tile& T, int bx0, int by0, int r) {
+template <class TT>
+__device__ __forceinline__ bool ring_covers_grid(const TT& T, int bx0, int by0, int r) {
   return bx0 - r <= 0 && by0 - r <= 0 && bx0 + r >= T.G - 1 && by0 + r >= T.G - 1;
 }
 
@@ -414,7 +436,8 @@ __device__ __forceinline__ bool ring_covers_grid(const Tile& T, int bx0, int by0
 // q's bucket; once a candidate exists, buckets farther from q than it are
 // skipped, and the search stops when the candidate is closer than the
 // nearest side of the square visited so far.
-__device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
+template <class TT>
+__device__ int ring_nearest(const TT& T, int qx, int qy, int skip) {
   const int G = T.G;
   const int bx0 = bucket_1d(qx + T.H, G, T.W2), by0 = bucket_1d(qy + T.H, G, T.W2);
   const double fx = qx + T.H, fy = qy + T.H;  // grid-local
@@ -475,7 +498,8 @@ __device__ int ring_nearest(const Tile& T, int qx, int qy, int skip) {
 // way, up to two rings; a lane still unproven then falls back to
 // ring_nearest.  Same order on (d^2, v, u), so the result equals
 // ring_nearest's.
-__device__ int nearest_block(const Tile& T, int q0, int C, int R, int bi, int bj, int lane, int& qx, int& qy) {
+template <class TT>
+__device__ int nearest_block(const TT& T, int q0, int C, int R, int bi, int bj, int lane, int& qx, int& qy) {
   const int G = T.G;
   const int i = bi * 8 + (lane >> 3), j = bj * 8 + (lane & 7);
   const bool in_grid = i < R && j < R;
@@ -537,11 +561,13 @@ __device__ int nearest_block(const Tile& T, int q0, int C, int R, int bi, int bj
 struct BucketBox {
   int x0, x1, y0, y1;
 };
-__device__ __forceinline__ int bucket_clamped(const Tile& T, double w) {
+template <class TT>
+__device__ __forceinline__ int bucket_clamped(const TT& T, double w) {
   const double c = fmin(fmax(w, (double)-T.H), (double)(T.H - 1));
   return bucket_1d((int)c + T.H, T.G, T.W2);
 }
-__device__ __forceinline__ BucketBox bucket_box(const Tile& T, double x0, double x1, double y0, double y1,
+template <class TT>
+__device__ __forceinline__ BucketBox bucket_box(const TT& T, double x0, double x1, double y0, double y1,
                                                 double slack) {
   BucketBox r;
   r.x0 = bucket_clamped(T, floor(x0 - slack));
@@ -560,7 +586,8 @@ __device__ __forceinline__ BucketBox bucket_box(const Tile& T, double x0, double
 // part of its circumcircle on that side (for a centre on the right this is
 // the thin cap between the chord and the parallel tangent).  Inside the box,
 // buckets entirely right of the line or outside the circle are skipped.
-__device__ int third_left(const Tile& T, int a, int b) {
+template <class TT>
+__device__ int third_left(const TT& T, int a, int b) {
   const int2 A = T.uv[a], B = T.uv[b];
   const int ax = A.x, ay = A.y, bx = B.x, by = B.y;
   const int mx = (ax + bx) >> 1, my = (ay + by) >> 1;
@@ -785,7 +812,8 @@ __device__ __forceinline__ void edge_clip(int px, int py, int qx, int qy, double
 // widened by one texel, its two ends are settled with the exact test, and
 // the texels between them are filled without further tests (a triangle's
 // row section is an interval).
-__device__ void raster_triangle(const Tile& T, int a, int b, int c, int C, int R, uint64_t* __restrict__ fm) {
+template <class TT>
+__device__ void raster_triangle(const TT& T, int a, int b, int c, int C, int R, uint64_t* __restrict__ fm) {
   const int2 A = T.uv[a], B = T.uv[b], Cc = T.uv[c];
   const int ax = A.x, ay = A.y, bx = B.x, by = B.y, cx = Cc.x, cy = Cc.y;
   int i0, i1, j0, j1;
@@ -812,7 +840,8 @@ __device__ void raster_triangle(const Tile& T, int a, int b, int c, int C, int R
 }
 
 // Texel bounding box of triangle (a, b, c); false when it holds no texel.
-__device__ __forceinline__ bool tri_texel_box(const Tile& T, int a, int b, int c, int C, int R, int& i0, int& i1,
+template <class TT>
+__device__ __forceinline__ bool tri_texel_box(const TT& T, int a, int b, int c, int C, int R, int& i0, int& i1,
                                               int& j0, int& j1) {
   const int2 A = T.uv[a], B = T.uv[b], Cc = T.uv[c];
   texel_range(min(A.x, min(B.x, Cc.x)), max(A.x, max(B.x, Cc.x)), T.H, C, R, j0, j1);
@@ -828,7 +857,8 @@ constexpr int RASTER_LANES = 8;
 
 // raster_triangle's result, computed by the RASTER_LANES lanes of a group:
 // every texel of the box gets the exact top-left test.
-__device__ void raster_triangle_group(const Tile& T, uint64_t key, int C, int R, uint64_t* __restrict__ fm, int lane) {
+template <class TT>
+__device__ void raster_triangle_group(const TT& T, uint64_t key, int C, int R, uint64_t* __restrict__ fm, int lane) {
   const int a = (int)(key >> 42), b = (int)((key >> 21) & 0x1FFFFF), c = (int)(key & 0x1FFFFF);
   int i0, i1, j0, j1;
   if (!tri_texel_box(T, a, b, c, C, R, i0, i1, j0, j1)) return;
@@ -853,7 +883,8 @@ __device__ void raster_triangle_group(const Tile& T, uint64_t key, int C, int R,
 // Texels lying exactly on hull edge a->b get the triangle next to it.  Per
 // texel row the line crosses at most one texel centre, found exactly in
 // integers.
-__device__ void raster_hull_edge(const Tile& T, int a, int b, uint64_t key, int C, int R, uint64_t* __restrict__ fm) {
+template <class TT>
+__device__ void raster_hull_edge(const TT& T, int a, int b, uint64_t key, int C, int R, uint64_t* __restrict__ fm) {
   const int2 A = T.uv[a], B = T.uv[b];
   const int ax = A.x, ay = A.y, bx = B.x, by = B.y;
   int i0, i1, j0, j1;
@@ -1102,15 +1133,18 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
           }
         }
       __syncthreads();
-      Tile T;
-      T.uv = uv_lds ? s_uv : P.cuv + off;
-      T.boff = s_k;
+      // Phases c-e once per pointer kind: LDS pointers when the points and
+      // their attributes are staged in LDS, global ones otherwise.
+      double cz = 0.0;
+      bool has_dt = false;
+      auto phases = [&](auto uvp, auto Tz, auto Tc) {
+      TileT<decltype(uvp)> T;
+      T.uv = uvp;
+      T.boff = (LdsI32)s_k;
       T.G = G;
       T.H = H;
       T.W2 = W2;
       T.bw = (double)W2 / G;
-      const int32_t* Tz = attr_lds ? s_z : P.sz + off;
-      const uint64_t* Tc = attr_lds ? s_c : P.srgb + off;
       // ---- c. face map reset (the nearest points follow the stars)
       const int q0 = -H + C / 2;
       for (int tt = tid; tt < RR; tt += RB) fm[tt] = FACE_NONE;
@@ -1124,7 +1158,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
         }
       }
       // face keys pack three point indices in 21 bits each
-      const bool has_dt = (__builtin_amdgcn_readfirstlane(__syncthreads_or(noncol)) != 0) && m < (1 << 21);
+      has_dt = (__builtin_amdgcn_readfirstlane(__syncthreads_or(noncol)) != 0) && m < (1 << 21);
       if (m >= (1 << 21) && tid == 0) atomicOr(&s_flags, LS_TILE_DEGENERATE);
       // ---- d. Delaunay stars, rasterised into the face map
       uint64_t* __restrict__ tris = P.tris + 2 * (int64_t)off;
@@ -1312,7 +1346,7 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
         s_cz = v4[0];
       }
       __syncthreads();
-      const double cz = s_cz;
+      cz = s_cz;
       float4* __restrict__ out = reinterpret_cast<float4*>(P.x_out + (int64_t)k * RR * 8);
       for (int tt = tid; tt < RR; tt += RB) {
         double lv[4];
@@ -1327,6 +1361,11 @@ __global__ void __launch_bounds__(RB, 4) k_recon(ReconParams P) {
                                       (float)((double)((c >> 16) & 0xFFFF) * k65),
                                       (float)((double)((c >> 32) & 0xFFFF) * k65));
       }
+      };
+      if (attr_lds)
+        phases(UvLds{(LdsU64)s_uv}, (LdsI32)s_z, (LdsU64)s_c);
+      else
+        phases(UvGlobal{P.cuv + off}, (const int32_t*)(P.sz + off), (const uint64_t*)(P.srgb + off));
     if (tid == 0) {
       P.cz_out[k] = cz;
       int st = flags | s_flags;
