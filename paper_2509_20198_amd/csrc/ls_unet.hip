@@ -315,17 +315,32 @@ __device__ __forceinline__ uint32_t wm_pack(float lo, float hi) {
 
 // channels cc..cc+7 of part p at input-plane pixel (yy, xx) as BF16 bits
 // (FP32-stored parts rounded to nearest even); zero outside
-__device__ __forceinline__ uint4 wm_load8(const SrcPart& p, int b, int yy, int xx, int cc, int H, int W) {
+// The fields of one of a conv's two input parts, chosen per lane and held
+// in registers (a per-lane choice between two SrcPart references is read
+// through memory at every use, one dependent load after another).
+struct PartR {
+  const uint16_t* bf16;
+  const float* f32;
+  int h, w, stride, coff, up, oy, ox;
+};
+__device__ __forceinline__ PartR part_pick(bool first, const SrcPart& a, const SrcPart& b) {
+  PartR r;
+  r.bf16 = first ? a.bf16 : b.bf16;
+  r.f32 = first ? a.f32 : b.f32;
+  r.h = first ? a.h : b.h;
+  r.w = first ? a.w : b.w;
+  r.stride = first ? a.stride : b.stride;
+  r.coff = first ? a.coff : b.coff;
+  r.up = first ? a.up : b.up;
+  r.oy = first ? a.oy : b.oy;
+  r.ox = first ? a.ox : b.ox;
+  return r;
+}
+
+__device__ __forceinline__ uint4 wm_load8(const PartR& p, int b, int yy, int xx, int cc, int H, int W) {
   const uint4 z = make_uint4(0u, 0u, 0u, 0u);
   if (yy < 0 || xx < 0 || yy >= H || xx >= W) return z;
-  int sy, sx;
-  if (p.up) {
-    sy = yy >> 1;
-    sx = xx >> 1;
-  } else {
-    sy = yy - p.oy;
-    sx = xx - p.ox;
-  }
+  const int sy = p.up ? (yy >> 1) : yy - p.oy, sx = p.up ? (xx >> 1) : xx - p.ox;
   if (sy < 0 || sx < 0 || sy >= p.h || sx >= p.w) return z;
   const int64_t o = (((int64_t)b * p.h + sy) * p.w + sx) * p.stride + p.coff + cc;
   if (p.bf16) return *reinterpret_cast<const uint4*>(p.bf16 + o);
@@ -408,7 +423,7 @@ __global__ void __launch_bounds__(CT) k_wgrad_mfma(WgradArgs A) {
         if (ps + 2 * pp + h < p1) {
           if (kind < 2) {
             const int ky = (d >> 20) & 3, kx = (d >> 18) & 3, cc = d & 0x3FFFF;
-            v[h] = wm_load8(kind == 0 ? A.src.a : A.src.b, pb[h], A.y0 + py[h] + ky - 1, A.x0 + px[h] + kx - 1, cc,
+            v[h] = wm_load8(part_pick(kind == 0, A.src.a, A.src.b), pb[h], A.y0 + py[h] + ky - 1, A.x0 + px[h] + kx - 1, cc,
                             A.H, A.W);
           } else if (kind == 2) {
             v[h].x = 0x3F80u;  // BF16 1.0 in column N
@@ -540,7 +555,7 @@ __global__ void __launch_bounds__(CT) k_wgrad_tile(WgradArgs A) {
       const int pr = pix / 18, pc = pix - pr * 18;
       const int g8 = gbase + gi;
       const bool in_a = 8 * g8 < A.src.a.c;
-      const uint4 v = wm_load8(in_a ? A.src.a : A.src.b, b, A.y0 + ty0 + pr - 1, A.x0 + tx0 + pc - 1,
+      const uint4 v = wm_load8(part_pick(in_a, A.src.a, A.src.b), b, A.y0 + ty0 + pr - 1, A.x0 + tx0 + pc - 1,
                                in_a ? 8 * g8 : 8 * g8 - A.src.a.c, A.H, A.W);
       const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
