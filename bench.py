@@ -137,6 +137,17 @@ def achievable_peaks(dev):
             "how": "torch copy_ of 1 GiB (bytes read + written); torch.matmul of two 8192x8192 BF16 matrices"}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(work, sample_idx, gpu_tex_bf16, gpu_tex_fp32, weights64):
     """The FP64 oracle (recon + network forward) on a strided sample of the
     batch, timed on the host cores; also the GPU error on those tiles."""
@@ -156,6 +167,12 @@ def cpu_baseline(work, sample_idx, gpu_tex_bf16, gpu_tex_fp32, weights64):
     base = oracle.texture(xo[:, work.region.pad:work.region.pad + work.region.res,
                              work.region.pad:work.region.pad + work.region.res][..., [0, 2, 3, 4]], cz, work.region)
     head_rms = np.sqrt(((tex[..., 0] - base[..., 0]) ** 2).reshape(len(tl), -1).mean(1))
+    # one thread on a sub-sample (the figure comparable to a single-threaded CPU pipeline)
+    tl1 = tl[:: max(1, len(tl) // 16)][:16]
+    t1 = time.perf_counter()
+    xo1, _, _ = oracle.recon_tiles(work.region, x, y, z, rgb, tl1, nthreads=1)
+    oracle.unet_forward(weights64, xo1, work.region.res, work.region.pad, nthreads=1)
+    dt1 = time.perf_counter() - t1
     return {
         "value": len(tl) / dt,
         "unit": "tiles/s",
@@ -163,6 +180,10 @@ def cpu_baseline(work, sample_idx, gpu_tex_bf16, gpu_tex_fp32, weights64):
         "kind": "oracle",
         "sample": f"{len(tl)} tiles (every {len(work.tile_list) // len(tl)}th of the batch): FP64 binning, "
                   f"Algorithm 1, normalisation and network forward; wall {dt:.2f} s",
+        "single_thread": {"tiles_per_s": len(tl1) / dt1, "ms_per_tile": dt1 / len(tl1) * 1e3,
+                          "sample": f"{len(tl1)} of those tiles, one thread"},
+        "cpu_model": cpu_model(),
+        "host_threads": os.cpu_count(),
     }, {
         "bf16_rms_max_m": float(rms16.max()),
         "bf16_rms_mean_m": float(rms16.mean()),
