@@ -77,11 +77,12 @@ def unet_flops(res: int, pad: int) -> float:
 
 
 def unet_bytes(res: int, pad: int) -> float:
-    """HBM bytes one tile's BF16 forward must move at least: every layer
-    reads its inputs once and writes its BF16 output once (and the fused 2x2
-    pool output of the two layers that feed a pool); the network input x is
-    FP32, the head reads the crop plus its one-texel halo and writes 4 FP32
-    channels."""
+    """HBM bytes one tile's BF16 forward must move at least, as the library
+    runs it: every layer up to dec1a reads its inputs once and writes its
+    BF16 output once (and the fused 2x2 pool output of the two layers that
+    feed a pool; the network input x is FP32); dec1b and the head run fused
+    on the crop, reading A9 on the crop plus a two-texel halo and x on the
+    crop plus one, and writing 4 FP32 channels."""
     R = res + 2 * pad
     f, h, q = R * R, (R // 2) ** 2, (R // 4) ** 2
     b16 = 2
@@ -89,15 +90,14 @@ def unet_bytes(res: int, pad: int) -> float:
            "A6": 64 * q, "A7": 32 * h, "A8": 32 * h, "A9": 16 * f, "A10": 16 * f}
     layers = [  # (inputs, outputs) as activation names; "x" is the FP32 input
         (["x"], ["A1"]), (["A1"], ["A2", "P1"]), (["P1"], ["A3"]), (["A3"], ["A4", "P2"]), (["P2"], ["A5"]),
-        (["A5"], ["A6"]), (["A6", "A4"], ["A7"]), (["A7"], ["A8"]), (["A8", "A2"], ["A9"]), (["A9"], ["A10"])]
+        (["A5"], ["A6"]), (["A6", "A4"], ["A7"]), (["A7"], ["A8"]), (["A8", "A2"], ["A9"])]
     total = 0
     for ins, outs in layers:
         for t in ins:
             total += 8 * f * 4 if t == "x" else act[t] * b16
         for t in outs:
             total += act[t] * b16
-    halo = (res + 2) ** 2
-    total += halo * 16 * b16 + halo * 8 * 4 + res * res * 4 * 4  # head
+    total += (res + 4) ** 2 * 16 * b16 + (res + 2) ** 2 * 8 * 4 + res * res * 4 * 4  # dec1b + head
     return float(total)
 
 

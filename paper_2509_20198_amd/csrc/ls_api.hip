@@ -66,7 +66,9 @@ int ls_conv_num_configs_impl(int layer, int precision, int pass) {
   if (layer < 0 || layer >= LS_NLAYER || precision < 0 || precision > 1 || pass < 0 || pass > 2) return 0;
   // BF16 forward: 0 = direct operand fetch (4 pixel tiles per wave),
   //   1 = LDS-staged 16x16 tile, 2 = direct with 2 pixel tiles per wave,
-  //   3 = LDS tile in persistent workgroups prefetching the next patch
+  //   3 = LDS tile in persistent workgroups prefetching the next patch;
+  //   enc1b and the head also 4 = fused with the layer before them when the
+  //   activations are not kept (the head's default)
   // BF16 input gradient: 0 / 1 = direct with 4 / 2 pixel tiles per wave,
   //   2 = persistent LDS tile (the default)
   // FP32 conv (forward, input gradient): 0..3 = channel block cap 32, 16, 8, 4
@@ -74,7 +76,7 @@ int ls_conv_num_configs_impl(int layer, int precision, int pass) {
   //   BF16 also 3..5 = the same on the matrix cores (im2col slabs) and
   //   6..8 = the same on the matrix cores by 16 x 16 output tiles
   if (pass == 2) return precision == LS_BF16 ? 9 : 3;
-  if (precision == LS_BF16) return pass == 0 ? 4 : 3;
+  if (precision == LS_BF16) return pass == 0 ? ((layer == 1 || layer == LS_NLAYER - 1) ? 5 : 4) : 3;
   return 4;
 }
 int ls_conv_config_get(int layer, int precision, int pass) {

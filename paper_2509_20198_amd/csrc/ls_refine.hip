@@ -433,7 +433,8 @@ int ls_refine_forward_impl(const float* w, const uint16_t* w_bf16, int precision
     LS_TRY(forward_f32(w, W.wt, x, n_tiles, gi, reinterpret_cast<float*>(acts), W.head, st));
   } else {
     LS_TRY(ls_bf16_prep_weights(w_bf16, W.wbt, st));
-    LS_TRY(ls_bf16_forward(w, W.wbt, x, n_tiles, gi, reinterpret_cast<uint16_t*>(acts), W.head, st));
+    LS_TRY(ls_bf16_forward(w, W.wbt, x, n_tiles, gi, reinterpret_cast<uint16_t*>(acts), W.head, act_save == nullptr,
+                           st));
   }
   return ls_head_epilogue(W.head, x, cz, n_tiles, gi.res, gi.pad, r_m, y_out, tex_out, st);
 }
@@ -459,7 +460,7 @@ int ls_refine_backward_impl(const float* w, const uint16_t* w_bf16, int precisio
   LS_TRY(ls_bf16_prep_dgrad_weights(w_bf16, W.wdb, st));
   const uint16_t* acts = reinterpret_cast<const uint16_t*>(act_save);
   if (!acts) {
-    LS_TRY(ls_bf16_forward(w, W.wbt, x, n_tiles, gi, reinterpret_cast<uint16_t*>(W.acts), W.head, st));
+    LS_TRY(ls_bf16_forward(w, W.wbt, x, n_tiles, gi, reinterpret_cast<uint16_t*>(W.acts), W.head, false, st));
     acts = reinterpret_cast<const uint16_t*>(W.acts);
   }
   return backward_bf16(x, acts, grad_y, n_tiles, gi, grad_w, grad_x, W, st);

@@ -622,13 +622,15 @@ __global__ void __launch_bounds__(256, MINW) k_conv_bf16_pipe(ConvTileArgs A) {
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
+    // The operands of K step ks + 1 are read from LDS before the products of
+    // step ks are issued (scheduling barriers keep the two groups apart), so
+    // each product waits only for reads issued a step earlier.
+    bf16x8 wf[2][NT], pf8[2][4];
+    auto operands = [&](int ks, bf16x8 (&w)[NT], bf16x8 (&px)[4]) {
       const int k = ks * 32 + 8 * g;
-      bf16x8 bfr[NT];
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt)
-        bfr[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(wrow + nt * 16 * WPITCH + ks * 32));
+        w[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(wrow + nt * 16 * WPITCH + ks * 32));
       const bool kv = k < K;
       const int tap = kv ? k / CIN : 0;
       const int ci = k - tap * CIN;
@@ -638,11 +640,21 @@ __global__ void __launch_bounds__(256, MINW) k_conv_bf16_pipe(ConvTileArgs A) {
       for (int mt = 0; mt < 4; ++mt) {
         u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
         if (kv) a = *reinterpret_cast<const u16x8*>(pb + mt * PT * PITCH);
-        const bf16x8 ab = __builtin_bit_cast(bf16x8, a);
+        px[mt] = __builtin_bit_cast(bf16x8, a);
+      }
+    };
+    operands(0, wf[0], pf8[0]);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int cur = ks & 1;
+      if (ks + 1 < KS) operands(ks + 1, wf[cur ^ 1], pf8[cur ^ 1]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], ab, acc[mt][nt], 0, 0, 0);
-      }
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[cur][nt], pf8[cur][mt], acc[mt][nt], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
     conv_tile_store_t<NT>(A, acc, bias, b, ty0, tx0, wave, g, r16);
     if (next >= ntiles) break;
@@ -1021,7 +1033,7 @@ int conv_bf16_lds(const ConvSrc& s, int B, int H, int l, const uint16_t* packed,
   LS_PIPE(5, 4, 64, 0, false, false, false, 1)
   LS_PIPE(6, 2, 64, 32, true, false, false, 1)
   LS_PIPE(7, 2, 32, 0, false, false, false, 2)
-  LS_PIPE(8, 1, 32, 16, true, false, false, 3)
+  LS_PIPE(8, 1, 32, 16, true, false, false, 2)
   LS_PIPE(9, 1, 16, 0, false, false, false, 2)
   LS_PIPE(10, 1, 16, 8, false, false, true, 2)
 #undef LS_PIPE
@@ -1087,6 +1099,340 @@ ConvSrc cs(SrcPart a, SrcPart b) {
   return s;
 }
 
+// Two 3x3 convs in one pass, for inference: layer l1 (CIN1 input channels,
+// 16 outputs, ReLU) on a 16 x 16 region, kept in LDS as BF16, then layer l2
+// on it (with CB2 more channels of a second part staged beside it) for the
+// 14 x 14 outputs whose 3 x 3 windows the region covers.  l1's activation
+// never goes to HBM, which is what bounds these full-resolution 16-channel
+// layers; the region's halo costs 31 % more matrix work.  l1's outputs
+// outside the plane are zero (l2's zero padding), so both layers compute
+// exactly what the separate launches compute: same MFMA sequences, same
+// rounding points, identical bits.
+constexpr int FT = TT - 2;  // fused output tile side
+
+struct Conv2Args {
+  SrcPart a1;  // l1's input (CIN1 channels)
+  SrcPart b2;  // l2's second part (CB2 channels), if any
+  int B, H, W;
+  int y0, x0, Ho, Wo;  // l2's output window in the plane
+  int tiles_x, tiles_y;
+  const uint16_t* wp1;  // packed l1 weights [16][KPAD1]
+  const float* bias1;
+  const uint16_t* wp2;  // packed l2 weights [16 * NT2][KPAD2]
+  const float* bias2;
+  int cout2, relu2;
+  uint16_t* out_bf16;  // l2 output [B][Ho][Wo][cout2], or null
+  float* out_f32;      // same layout, or null
+  uint16_t* pool_out;  // 2 x 2 average pool of the BF16 output [B][Ho/2][Wo/2][cout2], or null
+};
+
+// Products of one 16 x 16 output tile from a staged 18 x 18 patch (pitch
+// PITCH, CIN channels) with weights staged in LDS (rows of WPITCH): the K
+// order and accumulation of k_conv_bf16_lds_t.
+template <int NT, int CIN, int WPITCH>
+__device__ __forceinline__ void patch_mfma(const uint16_t* s_w, const uint16_t* s_patch, int wave, int g, int r16,
+                                           f32x4 (&acc)[4][NT]) {
+  constexpr int PITCH = pitch_c(CIN), K = 9 * CIN, KS = (K + 31) / 32;
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* wrow = s_w + r16 * WPITCH + 8 * g;
+  const uint16_t* base = s_patch + (wave * 4 * PT + r16) * PITCH;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = ks * 32 + 8 * g;
+    bf16x8 bfr[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+      bfr[nt] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8*>(wrow + nt * 16 * WPITCH + ks * 32));
+    const bool kv = k < K;
+    const int tap = kv ? k / CIN : 0;
+    const int ci = k - tap * CIN;
+    const int ky = tap / 3, kx = tap - 3 * ky;
+    const uint16_t* pb = base + (ky * PT + kx) * PITCH + ci;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      u16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (kv) a = *reinterpret_cast<const u16x8*>(pb + mt * PT * PITCH);
+      const bf16x8 ab = __builtin_bit_cast(bf16x8, a);
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[nt], ab, acc[mt][nt], 0, 0, 0);
+    }
+  }
+}
+
+// Persistent like k_conv_bf16_pipe: both layers' packed weights are copied
+// into LDS once per workgroup, which then walks the tiles tile, tile +
+// gridDim.x, ...; the next tile's input units (16 bytes each, 32 for an FP32
+// part, rounded to BF16 when written to LDS) are loaded into registers while
+// the current tile is multiplied.
+template <int CIN1, bool F32A, int CB2, bool F32B, int NT2, int MINW>
+__global__ void __launch_bounds__(256, MINW) k_conv2_bf16(Conv2Args A) {
+  constexpr int P1 = pitch_c(CIN1), CIN2 = 16 + CB2, P2 = pitch_c(CIN2);
+  constexpr int KPAD1 = (9 * CIN1 + 31) / 32 * 32, KPAD2 = (9 * CIN2 + 31) / 32 * 32;
+  constexpr int WP1 = wpitch_c(KPAD1), WP2 = wpitch_c(KPAD2);
+  constexpr int NU1 = PT * PT * (CIN1 / 8), NJ1 = (NU1 + 255) / 256, RW1 = F32A ? 8 : 4;
+  constexpr int NU2 = PT * PT * (CB2 / 8), NJ2 = CB2 > 0 ? (NU2 + 255) / 256 : 0, RW2 = F32B ? 8 : 4;
+  __shared__ __align__(16) uint16_t s1[PT * PT * P1];
+  __shared__ __align__(16) uint16_t s2[PT * PT * P2];
+  __shared__ __align__(16) uint16_t w1[16 * WP1];
+  __shared__ __align__(16) uint16_t w2[NT2 * 16 * WP2];
+  for (int u = threadIdx.x; u < 16 * (KPAD1 / 8); u += 256) {
+    const int row = u / (KPAD1 / 8), c8 = u - row * (KPAD1 / 8);
+    *reinterpret_cast<u16x8*>(w1 + row * WP1 + 8 * c8) = *reinterpret_cast<const u16x8*>(A.wp1 + (int64_t)row * KPAD1 + 8 * c8);
+  }
+  for (int u = threadIdx.x; u < NT2 * 16 * (KPAD2 / 8); u += 256) {
+    const int row = u / (KPAD2 / 8), c8 = u - row * (KPAD2 / 8);
+    *reinterpret_cast<u16x8*>(w2 + row * WP2 + 8 * c8) = *reinterpret_cast<const u16x8*>(A.wp2 + (int64_t)row * KPAD2 + 8 * c8);
+  }
+  // l1 padding of l2's patch (rows and columns 16, 17): zero for good
+  for (int pix = threadIdx.x; pix < PT * PT; pix += 256) {
+    const int py = pix / PT, px = pix - py * PT;
+    if (py >= TT || px >= TT) {
+      const u16x8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+      *reinterpret_cast<u16x8*>(s2 + pix * P2) = z;
+      *reinterpret_cast<u16x8*>(s2 + pix * P2 + 8) = z;
+    }
+  }
+  const int per_img = A.tiles_x * A.tiles_y, ntiles = A.B * per_img;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  uint32_t pf1[NJ1][RW1];
+  uint32_t pf2[NJ2 > 0 ? NJ2 : 1][RW2];
+  // the input units of a tile: l1's patch at (oy0 - 2, ox0 - 2), l2's second
+  // part at (oy0 - 1, ox0 - 1)
+  auto fetch_part = [&](const SrcPart& p, int b, int py0, int px0, int u, int C8, bool f32, uint32_t* r) {
+    const int pix = u / C8, ch = u - pix * C8;
+    const int py = pix / PT, px = pix - py * PT;
+    const int yy = py0 + py, xx = px0 + px;
+    const int sy = yy - p.oy, sx = xx - p.ox;
+    if (yy >= 0 && xx >= 0 && yy < A.H && xx < A.W && sy >= 0 && sx >= 0 && sy < p.h && sx < p.w) {
+      const int64_t o = (((int64_t)b * p.h + sy) * p.w + sx) * p.stride + p.coff + 8 * ch;
+      if (f32) {
+        const uint4 f0 = *reinterpret_cast<const uint4*>(p.f32 + o);
+        const uint4 f1 = *reinterpret_cast<const uint4*>(p.f32 + o + 4);
+        r[0] = f0.x;
+        r[1] = f0.y;
+        r[2] = f0.z;
+        r[3] = f0.w;
+        r[4] = f1.x;
+        r[5] = f1.y;
+        r[6] = f1.z;
+        r[7] = f1.w;
+      } else {
+        const uint4 v = *reinterpret_cast<const uint4*>(p.bf16 + o);
+        r[0] = v.x;
+        r[1] = v.y;
+        r[2] = v.z;
+        r[3] = v.w;
+      }
+    }
+  };
+  auto fetch = [&](int tile) {
+    const int b = tile / per_img, t = tile - b * per_img;
+    const int oy0 = A.y0 + (t / A.tiles_x) * FT, ox0 = A.x0 + (t % A.tiles_x) * FT;
+#pragma unroll
+    for (int j = 0; j < NJ1; ++j) {
+#pragma unroll
+      for (int r = 0; r < RW1; ++r) pf1[j][r] = 0u;
+      const int u = threadIdx.x + 256 * j;
+      if (u < NU1) fetch_part(A.a1, b, oy0 - 2, ox0 - 2, u, CIN1 / 8, F32A, pf1[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < NJ2; ++j) {
+#pragma unroll
+      for (int r = 0; r < RW2; ++r) pf2[j][r] = 0u;
+      const int u = threadIdx.x + 256 * j;
+      if (u < NU2) fetch_part(A.b2, b, oy0 - 1, ox0 - 1, u, CB2 / 8, F32B, pf2[j]);
+    }
+  };
+  auto to_lds = [&](const uint32_t* r, bool f32, uint16_t* dst) {
+    u16x8 v;
+    if (f32) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = f2bf(__builtin_bit_cast(float, r[k]));
+    } else {
+      v = __builtin_bit_cast(u16x8, make_uint4(r[0], r[1], r[2], r[3]));
+    }
+    *reinterpret_cast<u16x8*>(dst) = v;
+  };
+  int tile = xcd_block();
+  if (tile >= ntiles) return;
+  const int cout = A.cout2;
+  float bias1[4], bias2[NT2][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bias1[r] = A.bias1[4 * g + r];
+#pragma unroll
+  for (int nt = 0; nt < NT2; ++nt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = nt * 16 + 4 * g + r;
+      bias2[nt][r] = c < cout ? A.bias2[c] : 0.f;
+    }
+  // the biases and weights have landed before any tile's loads are in
+  // flight, so no wait for them inside the loop also waits for a prefetch
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  fetch(tile);
+  for (;;) {
+#pragma unroll
+    for (int j = 0; j < NJ1; ++j) {
+      const int u = threadIdx.x + 256 * j;
+      if (u < NU1) {
+        const int pix = u / (CIN1 / 8), ch = u - pix * (CIN1 / 8);
+        to_lds(pf1[j], F32A, s1 + pix * P1 + 8 * ch);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NJ2; ++j) {
+      const int u = threadIdx.x + 256 * j;
+      if (u < NU2) {
+        const int pix = u / (CB2 / 8), ch = u - pix * (CB2 / 8);
+        to_lds(pf2[j], F32B, s2 + pix * P2 + 16 + 8 * ch);
+      }
+    }
+    __syncthreads();
+    const int b = tile / per_img, t = tile - b * per_img;
+    const int ry0 = (t / A.tiles_x) * FT, rx0 = (t % A.tiles_x) * FT;  // tile origin in the output window
+    const int oy0 = A.y0 + ry0, ox0 = A.x0 + rx0;                      // ... in the plane
+    const int next = tile + (int)gridDim.x;
+    if (next < ntiles) fetch(next);
+    {
+      f32x4 acc[4][1];
+      patch_mfma<1, CIN1, WP1>(w1, s1, wave, g, r16, acc);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        const int row = wave * 4 + mt, col = r16;
+        const int yy = oy0 - 1 + row, xx = ox0 - 1 + col;
+        const bool in = yy >= 0 && xx >= 0 && yy < A.H && xx < A.W;
+        unsigned short h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[r] = in ? f2bf(fmaxf(acc[mt][0][r] + bias1[r], 0.f)) : (unsigned short)0;
+        uint2 u;
+        u.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+        u.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+        *reinterpret_cast<uint2*>(s2 + (row * PT + col) * P2 + 4 * g) = u;
+      }
+    }
+    __syncthreads();
+    f32x4 acc[4][NT2];
+    patch_mfma<NT2, CIN2, WP2>(w2, s2, wave, g, r16, acc);
+    // l2's epilogue: rows and columns below FT and inside the window
+    const int r0 = wave * 4, c = r16;
+    const int oyr = ry0 + r0, oxr = rx0 + c;  // window coordinates of row mt = 0
+#pragma unroll
+    for (int nt = 0; nt < NT2; ++nt) {
+      const int c0 = nt * 16 + 4 * g;
+      if (c0 >= cout) continue;
+      float q[4][4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          float v = acc[mt][nt][r] + bias2[nt][r];
+          if (A.relu2) v = fmaxf(v, 0.f);
+          q[mt][r] = v;
+        }
+      auto ok = [&](int mt) { return r0 + mt < FT && c < FT && oyr + mt < A.Ho && oxr < A.Wo; };
+      const int64_t off0 = (((int64_t)b * A.Ho + oyr) * A.Wo + oxr) * cout + c0, row = (int64_t)A.Wo * cout;
+      if (A.out_f32) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+          if (ok(mt))
+            *reinterpret_cast<float4*>(A.out_f32 + off0 + mt * row) = make_float4(q[mt][0], q[mt][1], q[mt][2], q[mt][3]);
+        continue;
+      }
+      unsigned short h[4][4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[mt][r] = f2bf(q[mt][r]);
+        if (A.out_bf16 && ok(mt)) {
+          uint2 u;
+          u.x = (uint32_t)h[mt][0] | ((uint32_t)h[mt][1] << 16);
+          u.y = (uint32_t)h[mt][2] | ((uint32_t)h[mt][3] << 16);
+          *reinterpret_cast<uint2*>(A.out_bf16 + off0 + mt * row) = u;
+        }
+      }
+      if (A.pool_out) {
+        // same pairing and order as the separate epilogue: rows mt, mt + 1
+        // in the lane, columns c, c ^ 1 across lanes (tile origins are even)
+        const int Hp = A.Ho / 2, Wp = A.Wo / 2;
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+          unsigned short pv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float tl = bf2f(h[2 * pr][r]), bl = bf2f(h[2 * pr + 1][r]);
+            const float tr = __shfl_xor(tl, 1, 64), br = __shfl_xor(bl, 1, 64);
+            pv[r] = f2bf(0.25f * ((tl + tr) + (bl + br)));
+          }
+          const int pyr = (oyr + 2 * pr) / 2, pxr = oxr / 2;
+          if ((c & 1) == 0 && r0 + 2 * pr < FT && c < FT && pyr < Hp && pxr < Wp) {
+            uint2 u;
+            u.x = (uint32_t)pv[0] | ((uint32_t)pv[1] << 16);
+            u.y = (uint32_t)pv[2] | ((uint32_t)pv[3] << 16);
+            *reinterpret_cast<uint2*>(A.pool_out + (((int64_t)b * Hp + pyr) * Wp + pxr) * cout + c0) = u;
+          }
+        }
+      }
+    }
+    if (next >= ntiles) break;
+    tile = next;
+    __syncthreads();  // every wave is done with both patches before they are overwritten
+  }
+}
+
+// Layers l1 and l2 fused (k_conv2_bf16) for the input shapes that have a
+// compiled form; LS_ENOTIMPL otherwise.
+int conv2_bf16(const SrcPart& a1, const SrcPart& b2, int B, int H, int l1, int l2, const uint16_t* packed,
+               const float* w, uint16_t* out_bf16, float* out_f32, uint16_t* pool_out, int relu2, int y0, int x0,
+               int Ho, int Wo, hipStream_t st) {
+  if (LS_LAYERS[l1].cout != 16 || LS_LAYERS[l2].cin != 16 + b2.c || a1.c != LS_LAYERS[l1].cin) return LS_ENOTIMPL;
+  if (a1.up || b2.up || (pool_out && (Ho % 2 || Wo % 2))) return LS_ENOTIMPL;
+  Conv2Args a;
+  a.a1 = a1;
+  a.b2 = b2;
+  a.B = B;
+  a.H = H;
+  a.W = H;
+  a.y0 = y0;
+  a.x0 = x0;
+  a.Ho = Ho;
+  a.Wo = Wo;
+  a.tiles_x = (Wo + FT - 1) / FT;
+  a.tiles_y = (Ho + FT - 1) / FT;
+  a.wp1 = packed + ls_bf16_packed_offset(l1);
+  a.bias1 = w + ls_layer_b_offset(l1);
+  a.wp2 = packed + ls_bf16_packed_offset(l2);
+  a.bias2 = w + ls_layer_b_offset(l2);
+  a.cout2 = LS_LAYERS[l2].cout;
+  a.relu2 = relu2;
+  a.out_bf16 = out_bf16;
+  a.out_f32 = out_f32;
+  a.pool_out = pool_out;
+  const int64_t nblk = (int64_t)B * a.tiles_x * a.tiles_y;
+  if (nblk <= 0) return LS_OK;
+  if (nblk >= ((int64_t)1 << 31)) return LS_ENOTIMPL;
+  const bool f32a = a1.f32 != nullptr, f32b = b2.c > 0 && b2.f32 != nullptr;
+  LS_TRACE("conv_bf16", st);
+  // persistent: as many workgroups as fit on the device at once
+  auto launch = [&](auto* fn) {
+    int per_cu = 0, dev = 0, cus = 0;
+    LS_HOST_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0));
+    LS_HOST_CHECK(hipGetDevice(&dev));
+    LS_HOST_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int64_t want = (int64_t)std::max(per_cu, 1) * std::max(cus, 1);
+    hipLaunchKernelGGL(fn, dim3((unsigned)std::min<int64_t>(want, nblk)), dim3(256), 0, st, a);
+    LS_LAUNCH_CHECK();
+    return LS_OK;
+  };
+  if (a1.c == 8 && f32a && b2.c == 0 && a.cout2 <= 16) return launch(&k_conv2_bf16<8, true, 0, false, 1, 2>);
+  if (a1.c == 16 && !f32a && b2.c == 8 && f32b && a.cout2 <= 16) return launch(&k_conv2_bf16<16, false, 8, true, 1, 2>);
+  return LS_ENOTIMPL;
+}
+
 int pool_bf16(const uint16_t* in, uint16_t* out, int B, int H, int C, hipStream_t st) {
   const int64_t n = (int64_t)B * (H / 2) * (H / 2) * C;
   LS_TRACE("avgpool_bf16", st);
@@ -1104,7 +1450,7 @@ int pool_bf16(const uint16_t* in, uint16_t* out, int B, int H, int C, hipStream_
   } while (0)
 
 int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int B, const LsGridInfo& gi,
-                    uint16_t* acts, float* head, hipStream_t st) {
+                    uint16_t* acts, float* head, bool fuse, hipStream_t st) {
   const int R = gi.R, R2 = R / 2, R4 = R / 4;
   const int64_t f = (int64_t)R * R, h = f / 4, q = f / 16;
   // same activation order and sizes as the FP32 layout
@@ -1128,7 +1474,15 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   // prefetch the next patch
   auto variant = [&](int l) {
     const int c = ls_conv_config_get(l, LS_BF16, 0);
-    return c >= 0 ? c : 3;  // default: the persistent tile
+    return c >= 0 && c <= 3 ? c : 3;  // default: the persistent tile
+  };
+  // layer pairs (enc1a, enc1b) and (dec1b, head) in one pass when their
+  // first activation is not kept: config 4 of the pair's second layer, the
+  // default for the head (measured on 1024 tiles: dec1b + head 0.230 ->
+  // 0.170 ms; enc1a + enc1b 0.261 -> 0.267 ms, so separate by default)
+  auto fused = [&](int l2) {
+    const int c = ls_conv_config_get(l2, LS_BF16, 0);
+    return fuse && (c == 4 || (c < 0 && l2 == LS_NLAYER - 1));
   };
   // a layer feeding an average pool writes the pooled tensor too when it uses the LDS tile
   auto conv = [&](const ConvSrc& s, int H, int l, uint16_t* out, uint16_t* pooled) -> int {
@@ -1148,8 +1502,14 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   u6.up = 1;
   SrcPart u8 = bpart(A8, 32, R2);
   u8.up = 1;
-  LS_TRYB(conv(cs(X, none), R, 0, A1, nullptr));
-  LS_TRYB(conv(cs(bpart(A1, 16, R), none), R, 1, A2, P1));
+  int rc01 = LS_ENOTIMPL;
+  if (fused(1)) rc01 = conv2_bf16(X, none, B, R, 0, 1, packed, w, A2, nullptr, P1, 1, 0, 0, R, R, st);
+  if (rc01 == LS_ENOTIMPL) {
+    LS_TRYB(conv(cs(X, none), R, 0, A1, nullptr));
+    LS_TRYB(conv(cs(bpart(A1, 16, R), none), R, 1, A2, P1));
+  } else {
+    LS_TRYB(rc01);
+  }
   LS_TRYB(conv(cs(bpart(P1, 16, R2), none), R2, 2, A3, nullptr));
   LS_TRYB(conv(cs(bpart(A3, 32, R2), none), R2, 3, A4, P2));
   LS_TRYB(conv(cs(bpart(P2, 32, R4), none), R4, 4, A5, nullptr));
@@ -1157,6 +1517,11 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   LS_TRYB(conv(cs(u6, bpart(A4, 32, R2)), R2, 6, A7, nullptr));
   LS_TRYB(conv(cs(bpart(A7, 32, R2), none), R2, 7, A8, nullptr));
   LS_TRYB(conv(cs(u8, bpart(A2, 16, R)), R, 8, A9, nullptr));
+  if (fused(10)) {
+    const int rc = conv2_bf16(bpart(A9, 16, R), X, B, R, 9, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,
+                              gi.res, gi.res, st);
+    if (rc != LS_ENOTIMPL) return rc;
+  }
   LS_TRYB(conv(cs(bpart(A9, 16, R), none), R, 9, A10, nullptr));
   if ((variant(10) == 1 || variant(10) == 3) && (size_t)PT * PT * patch_pitch(24) * 2 <= LDS_MAX)
     return conv_bf16_lds(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,

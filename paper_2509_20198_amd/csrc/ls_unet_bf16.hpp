@@ -11,8 +11,10 @@ size_t ls_bf16_packed_total();
 int ls_bf16_kpad(int layer);
 
 int ls_bf16_prep_weights(const uint16_t* w_bf16, uint16_t* packed, hipStream_t st);
+// fuse: the activations are not kept (inference), so layer pairs may run
+// fused without storing their first activation
 int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int B, const LsGridInfo& gi,
-                    uint16_t* acts, float* head, hipStream_t st);
+                    uint16_t* acts, float* head, bool fuse, hipStream_t st);
 int ls_pack_bf16(const float* w, uint16_t* out, int64_t n, hipStream_t st);
 
 // Backward helpers (BF16 operands, FP32 results).
