@@ -1516,12 +1516,24 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   LS_TRYB(conv(cs(bpart(A5, 64, R4), none), R4, 5, A6, nullptr));
   LS_TRYB(conv(cs(u6, bpart(A4, 32, R2)), R2, 6, A7, nullptr));
   LS_TRYB(conv(cs(bpart(A7, 32, R2), none), R2, 7, A8, nullptr));
-  LS_TRYB(conv(cs(u8, bpart(A2, 16, R)), R, 8, A9, nullptr));
   if (fused(10)) {
-    const int rc = conv2_bf16(bpart(A9, 16, R), X, B, R, 9, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,
-                              gi.res, gi.res, st);
+    // dec1a only where the fused dec1b + head read it, the crop and a
+    // two-texel halo (clipped to the plane), stored as a window tensor
+    const int w0 = std::max(0, gi.pad - 2), w1 = std::min(R, gi.pad + gi.res + 2), Hw = w1 - w0;
+    if (variant(8) == 1 || variant(8) == 3)
+      LS_TRYB(conv_bf16_lds(cs(u8, bpart(A2, 16, R)), B, R, 8, packed, w, A9, nullptr, nullptr, 1, w0, w0, Hw, Hw,
+                            variant(8) == 3, st));
+    else
+      LS_TRYB(conv_bf16(cs(u8, bpart(A2, 16, R)), B, R, 8, packed, w, A9, nullptr, 1, w0, w0, Hw, Hw,
+                        variant(8) == 2 ? 2 : 4, st));
+    SrcPart a9 = bpart(A9, 16, Hw);
+    a9.oy = w0;
+    a9.ox = w0;
+    const int rc = conv2_bf16(a9, X, B, R, 9, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad, gi.res, gi.res,
+                              st);
     if (rc != LS_ENOTIMPL) return rc;
   }
+  LS_TRYB(conv(cs(u8, bpart(A2, 16, R)), R, 8, A9, nullptr));
   LS_TRYB(conv(cs(bpart(A9, 16, R), none), R, 9, A10, nullptr));
   if ((variant(10) == 1 || variant(10) == 3) && (size_t)PT * PT * patch_pitch(24) * 2 <= LDS_MAX)
     return conv_bf16_lds(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,
