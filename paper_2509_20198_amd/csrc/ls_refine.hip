@@ -355,24 +355,49 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
     return ls_bf16_dgrad(one(bsrc(g, LS_LAYERS[l].cout, H)), B, H, l, W.wdb, dX,
                          act_below >= 0 ? A(act_below) : nullptr, gb, st);
   };
-  // head: gradient embedded at the crop, padded to 8 channels
+  // head: gradient embedded at the crop, padded to 8 channels.  Its input
+  // gradient's first 16 channels (dA10) are masked and rounded in the
+  // epilogue when the persistent form runs; the last 8 (the gradient of the
+  // input skip) stay FP32, in dXC with xc_stride channels from xc_off.
   LS_TRY(ls_bf16_embed8(grad_y, W.gy8, (int64_t)B * res * res, st));
+  int xc_stride = 8, xc_off = 0;
   {
     SrcPart g = bsrc(W.gy8, 8, res);
     g.oy = pad;
     g.ox = pad;
-    LS_TRY(ls_bf16_dgrad(one(g), B, R, HEAD, W.wdb, W.dXC, nullptr, nullptr, st));
+    const int rc = ls_bf16_dgrad_split(one(g), B, R, HEAD, W.wdb, W.dXC, nullptr, 0, A(iA10), g0, 16, st);
+    if (rc == LS_ENOTIMPL) {
+      LS_TRY(ls_bf16_dgrad(one(g), B, R, HEAD, W.wdb, W.dXC, nullptr, nullptr, st));
+      // decoder level 1: dA10 is the first 16 of the head input's 24 channels
+      LS_TRY(ls_bf16_mask_round_ex(W.dXC, 24, 0, A(iA10), nullptr, B, R, 16, g0, st));
+      xc_stride = 24;
+      xc_off = 16;
+    } else {
+      LS_TRY(rc);
+    }
   }
   LS_TRY(wgrad_bf16(two(P(iA10, 16, R), X), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
-  // decoder level 1: dA10 is the first 16 of the head input's 24 channels
-  LS_TRY(ls_bf16_mask_round_ex(W.dXC, 24, 0, A(iA10), nullptr, B, R, 16, g0, st));
   LS_TRY(wg(D1B, g0, one(P(iA9, 16, R)), R));
   LS_TRY(dg(D1B, g0, R, nullptr, iA9, g1));
   SrcPart u8 = P(iA8, 32, R2);
   u8.up = 1;
   LS_TRY(wg(D1A, g1, two(u8, P(iA2, 16, R)), R));
-  LS_TRY(dg(D1A, g1, R, W.dU1, -1, nullptr));
-  LS_TRY(ls_up_adjoint(W.dU1, 48, W.dA8, B, R2, R2, 32, st));
+  // dU1: the upsampled part's 32 channels go straight to their upsampling
+  // adjoint dA8 when the persistent form runs, the skip part's 16 stay in
+  // dU1 (u1_stride channels from u1_off)
+  int u1_stride = 16, u1_off = 0;
+  {
+    const int rc = ls_bf16_dgrad_split(one(bsrc(g1, 16, R)), B, R, D1A, W.wdb, W.dU1, W.dA8, 32, nullptr, nullptr, 0,
+                                       st);
+    if (rc == LS_ENOTIMPL) {
+      LS_TRY(dg(D1A, g1, R, W.dU1, -1, nullptr));
+      LS_TRY(ls_up_adjoint(W.dU1, 48, W.dA8, B, R2, R2, 32, st));
+      u1_stride = 48;
+      u1_off = 32;
+    } else {
+      LS_TRY(rc);
+    }
+  }
   // decoder level 2
   LS_TRY(ls_bf16_mask_round_ex(W.dA8, 32, 0, A(iA8), nullptr, B, R2, 32, g0, st));
   LS_TRY(wg(D2B, g0, one(P(iA7, 32, R2)), R2));
@@ -380,8 +405,19 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   SrcPart u6 = P(iA6, 64, R4);
   u6.up = 1;
   LS_TRY(wg(D2A, g1, two(u6, P(iA4, 32, R2)), R2));
-  LS_TRY(dg(D2A, g1, R2, W.dU2, -1, nullptr));
-  LS_TRY(ls_up_adjoint(W.dU2, 96, W.dA6, B, R4, R4, 64, st));
+  int u2_stride = 32, u2_off = 0;
+  {
+    const int rc = ls_bf16_dgrad_split(one(bsrc(g1, 32, R2)), B, R2, D2A, W.wdb, W.dU2, W.dA6, 64, nullptr, nullptr,
+                                       0, st);
+    if (rc == LS_ENOTIMPL) {
+      LS_TRY(dg(D2A, g1, R2, W.dU2, -1, nullptr));
+      LS_TRY(ls_up_adjoint(W.dU2, 96, W.dA6, B, R4, R4, 64, st));
+      u2_stride = 96;
+      u2_off = 64;
+    } else {
+      LS_TRY(rc);
+    }
+  }
   // bottleneck
   LS_TRY(ls_bf16_mask_round_ex(W.dA6, 64, 0, A(iA6), nullptr, B, R4, 64, g0, st));
   LS_TRY(wg(BB, g0, one(P(iA5, 64, R4)), R4));
@@ -389,19 +425,19 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   LS_TRY(wg(BA, g1, one(P(iP2, 32, R4)), R4));
   LS_TRY(dg(BA, g1, R4, W.dP2, -1, nullptr));
   // encoder level 2: dA4 = skip slice of dU2 + pool adjoint of dP2
-  LS_TRY(ls_bf16_mask_round_ex(W.dU2, 96, 64, A(iA4), W.dP2, B, R2, 32, g0, st));
+  LS_TRY(ls_bf16_mask_round_ex(W.dU2, u2_stride, u2_off, A(iA4), W.dP2, B, R2, 32, g0, st));
   LS_TRY(wg(E2B, g0, one(P(iA3, 32, R2)), R2));
   LS_TRY(dg(E2B, g0, R2, nullptr, iA3, g1));
   LS_TRY(wg(E2A, g1, one(P(iP1, 16, R2)), R2));
   LS_TRY(dg(E2A, g1, R2, W.dP1, -1, nullptr));
   // encoder level 1: dA2 = skip slice of dU1 + pool adjoint of dP1
-  LS_TRY(ls_bf16_mask_round_ex(W.dU1, 48, 32, A(iA2), W.dP1, B, R, 16, g0, st));
+  LS_TRY(ls_bf16_mask_round_ex(W.dU1, u1_stride, u1_off, A(iA2), W.dP1, B, R, 16, g0, st));
   LS_TRY(wg(E1B, g0, one(P(iA1, 16, R)), R));
   LS_TRY(dg(E1B, g0, R, nullptr, iA1, g1));
   LS_TRY(wg(E1A, g1, one(X), R));
   if (grad_x) {
     LS_TRY(dg(E1A, g1, R, grad_x, -1, nullptr));
-    LS_TRY(ls_copy_channels(W.dXC, 24, 16, grad_x, 8, B * f, 1, st));
+    LS_TRY(ls_copy_channels(W.dXC, xc_stride, xc_off, grad_x, 8, B * f, 1, st));
     LS_TRY(ls_residual_adjoint(grad_y, grad_x, B, res, pad, st));
   }
   return LS_OK;

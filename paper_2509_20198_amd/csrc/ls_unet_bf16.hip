@@ -387,6 +387,35 @@ __device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f
         if (A.relu) v = fmaxf(v, 0.f);
         q[mt][r] = v;
       }
+    if (A.up_out && c0 < A.up_c) {
+      // 2 x 2 block sums, in the order of the separate upsampling adjoint:
+      // (top left + top right) + (bottom left + bottom right)
+      const int Hp = A.Ho / 2, Wp = A.Wo / 2;
+#pragma unroll
+      for (int pr = 0; pr < 2; ++pr) {
+        float sum[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float tl = q[2 * pr][r], bl = q[2 * pr + 1][r];
+          const float tr = __shfl_xor(tl, 1, 64), br = __shfl_xor(bl, 1, 64);
+          sum[r] = (tl + tr) + (bl + br);
+        }
+        const int py = (oy0 + 2 * pr) / 2, px = ox / 2;
+        if ((r16 & 1) == 0 && (full || (py < Hp && px < Wp)))
+          *reinterpret_cast<float4*>(A.up_out + (((int64_t)b * Hp + py) * Wp + px) * A.up_c + c0) =
+              make_float4(sum[0], sum[1], sum[2], sum[3]);
+      }
+      continue;
+    }
+    if (A.out2_f32 && c0 >= A.split) {
+      const int s2 = cout - A.split;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+        if (full || (oy0 + mt < A.Ho && ox < A.Wo))
+          *reinterpret_cast<float4*>(A.out2_f32 + (pix0 + (int64_t)mt * A.Wo) * s2 + (c0 - A.split)) =
+              make_float4(q[mt][0], q[mt][1], q[mt][2], q[mt][3]);
+      continue;
+    }
     const int64_t off0 = pix0 * ostr + A.out_coff + c0, row = (int64_t)A.Wo * ostr;
     if (A.out_f32) {
 #pragma unroll
@@ -884,6 +913,57 @@ int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked
   LS_TRACE("dgrad_bf16", st);
   const int mt = cfg == 1 ? 2 : 4;
   return launch_direct(a, (cin + 15) / 16, mt, (int64_t)B * H * H, st);
+}
+
+int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked, float* out, float* up_out,
+                        int up_c, const uint16_t* mask, uint16_t* out_masked, int split, hipStream_t st) {
+  const int cin = LS_LAYERS[l].cin;
+  if (s.a.c + s.b.c != dgrad_cg(l)) return LS_EINVAL;
+  const int cfg = ls_conv_config_get(l, LS_BF16, 1);
+  if (!(cfg < 0 || cfg == 2)) return LS_ENOTIMPL;
+  // whole 16-channel tiles on each side of the split; even planes for the 2 x 2 sums
+  if (up_c > 0 ? (up_c % 16 || up_c >= cin || H % 2) : (split <= 0 || split % 16 || split >= cin || !mask))
+    return LS_ENOTIMPL;
+  ConvTileArgs a;
+  a.src = s;
+  a.B = B;
+  a.H = H;
+  a.W = H;
+  a.y0 = 0;
+  a.x0 = 0;
+  a.Ho = H;
+  a.Wo = H;
+  a.tiles_x = (H + TT - 1) / TT;
+  a.tiles_y = (H + TT - 1) / TT;
+  a.wp = dpacked + ls_bf16_dpacked_offset(l);
+  a.Kpad = dgrad_kpad(l);
+  a.bias = nullptr;
+  a.cout = cin;
+  a.relu = 0;
+  a.pool_out = nullptr;
+  a.pool_stride = 0;
+  a.pool_coff = 0;
+  if (up_c > 0) {
+    // channels from up_c on: FP32, cin - up_c per pixel
+    a.out_bf16 = nullptr;
+    a.out_f32 = out;
+    a.out_stride = cin - up_c;
+    a.out_coff = -up_c;
+    a.mask = nullptr;
+    a.up_out = up_out;
+    a.up_c = up_c;
+  } else {
+    // channels below split: masked BF16, split per pixel
+    a.out_bf16 = out_masked;
+    a.out_f32 = nullptr;
+    a.out_stride = split;
+    a.out_coff = 0;
+    a.mask = mask;
+    a.split = split;
+    a.out2_f32 = out;
+  }
+  return ls_bf16_conv_pipe(a, (cin + 15) / 16, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr,
+                           s.b.c > 0 && s.b.f32 != nullptr, st, "dgrad_bf16");
 }
 
 int ls_bf16_kpad(int l) { return (9 * LS_LAYERS[l].cin + 31) / 32 * 32; }

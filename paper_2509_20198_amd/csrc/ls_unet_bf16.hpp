@@ -26,6 +26,14 @@ int ls_bf16_embed8(const float* g, uint16_t* out, int64_t npix, hipStream_t st);
 // mask given: instead of FP32 `out`, write out_masked = BF16(dX where mask > 0, else 0)
 int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, float* out, const uint16_t* mask,
                   uint16_t* out_masked, hipStream_t st);
+// The input gradient with its channels split (LS_ENOTIMPL unless the
+// persistent tile form runs): up_c > 0: channels [0, up_c) as the
+// upsampling adjoint into up_out (FP32, half resolution), the others FP32
+// into out (cin - up_c channels); else channels [0, split) masked by `mask`
+// into out_masked (BF16, split channels), the others FP32 into out
+// (cin - split channels).
+int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, float* out,
+                        float* up_out, int up_c, const uint16_t* mask, uint16_t* out_masked, int split, hipStream_t st);
 int ls_bf16_mask_round_ex(const float* src, int stride, int coff, const uint16_t* act, const float* low, int B, int H,
                           int C, uint16_t* out, hipStream_t st);
 
@@ -47,6 +55,13 @@ struct ConvTileArgs {
   uint16_t* pool_out;    // 2 x 2 average pool [B][Ho/2][Wo/2][pool_stride] at pool_coff, or null
   int pool_stride, pool_coff;
   const uint16_t* mask;  // BF16 output: zero where this activation (output layout) is not positive, or null
+  // input-gradient splits (persistent form): channels below up_c summed
+  // over 2 x 2 pixel blocks into up_out [B][Ho/2][Wo/2][up_c] (FP32), or
+  // channels from split on written to out2_f32 [B][Ho][Wo][cout - split]
+  float* up_out = nullptr;
+  int up_c = 0;
+  int split = 0;
+  float* out2_f32 = nullptr;
 };
 
 // Persistent pipelined BF16 conv (weights in LDS, next patch prefetched) on
