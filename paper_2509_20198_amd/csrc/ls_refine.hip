@@ -48,6 +48,7 @@ struct RefineWs {
   uint16_t* gz;
   uint16_t* gz2;
   uint16_t* gy8;
+  uint16_t* xb;  // the network input rounded to BF16 (read by the weight gradients of its two consumers)
 };
 
 size_t refine_layout(const LsGridInfo& gi, int32_t B, int precision, int backward, bool need_acts, void* base,
@@ -84,6 +85,7 @@ size_t refine_layout(const LsGridInfo& gi, int32_t B, int precision, int backwar
       W->gz = A.take<uint16_t>(B * 16 * f);
       W->gz2 = A.take<uint16_t>(B * 16 * f);
       W->gy8 = A.take<uint16_t>((int64_t)B * res * res * 8);
+      W->xb = A.take<uint16_t>(B * 8 * f);
     }
   }
   return A.used;
@@ -343,7 +345,6 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   const Acts al = act_layout(R);
   auto A = [&](int i) { return acts + al.off[i] * B; };
   auto P = [&](int i, int c, int hw) { return bsrc(A(i), c, hw); };
-  const SrcPart X = src_plain(x, 8, R, R, 8, 0, nullptr);
   uint16_t* const g0 = W.gz;
   uint16_t* const g1 = W.gz2;
   auto wg = [&](int l, const uint16_t* g, const ConvSrc& in, int H) -> int {
@@ -360,6 +361,12 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   // epilogue when the persistent form runs; the last 8 (the gradient of the
   // input skip) stay FP32, in dXC with xc_stride channels from xc_off.
   LS_TRY(ls_bf16_embed8(grad_y, W.gy8, (int64_t)B * res * res, st));
+  // x in BF16 once (the rounding the weight-gradient staging would apply)
+  {
+    LS_TRACE("embed8", st);
+    LS_TRY(ls_pack_bf16(x, W.xb, B * f * 8, st));
+  }
+  const SrcPart XB = bsrc(W.xb, 8, R);
   int xc_stride = 8, xc_off = 0;
   {
     SrcPart g = bsrc(W.gy8, 8, res);
@@ -376,7 +383,7 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
       LS_TRY(rc);
     }
   }
-  LS_TRY(wgrad_bf16(two(P(iA10, 16, R), X), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
+  LS_TRY(wgrad_bf16(two(P(iA10, 16, R), XB), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
   LS_TRY(wg(D1B, g0, one(P(iA9, 16, R)), R));
   LS_TRY(dg(D1B, g0, R, nullptr, iA9, g1));
   SrcPart u8 = P(iA8, 32, R2);
@@ -434,7 +441,7 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   LS_TRY(ls_bf16_mask_round_ex(W.dU1, u1_stride, u1_off, A(iA2), W.dP1, B, R, 16, g0, st));
   LS_TRY(wg(E1B, g0, one(P(iA1, 16, R)), R));
   LS_TRY(dg(E1B, g0, R, nullptr, iA1, g1));
-  LS_TRY(wg(E1A, g1, one(X), R));
+  LS_TRY(wg(E1A, g1, one(XB), R));
   if (grad_x) {
     LS_TRY(dg(E1A, g1, R, grad_x, -1, nullptr));
     LS_TRY(ls_copy_channels(W.dXC, xc_stride, xc_off, grad_x, 8, B * f, 1, st));

@@ -337,6 +337,15 @@ __device__ __forceinline__ PartR part_pick(bool first, const SrcPart& a, const S
   return r;
 }
 
+// Element offset of channels cc .. cc + 7 of part p at input pixel (yy, xx)
+// of image b, or -1 where the input is zero padding.
+__device__ __forceinline__ int64_t wm_offset8(const PartR& p, int b, int yy, int xx, int cc, int H, int W) {
+  if (yy < 0 || xx < 0 || yy >= H || xx >= W) return -1;
+  const int sy = p.up ? (yy >> 1) : yy - p.oy, sx = p.up ? (xx >> 1) : xx - p.ox;
+  if (sy < 0 || sx < 0 || sy >= p.h || sx >= p.w) return -1;
+  return (((int64_t)b * p.h + sy) * p.w + sx) * p.stride + p.coff + cc;
+}
+
 __device__ __forceinline__ uint4 wm_load8(const PartR& p, int b, int yy, int xx, int cc, int H, int W) {
   const uint4 z = make_uint4(0u, 0u, 0u, 0u);
   if (yy < 0 || xx < 0 || yy >= H || xx >= W) return z;
@@ -506,8 +515,10 @@ constexpr int WT_GROUPS = 2;            // 8-channel input groups per workgroup
 constexpr int WT_PITCH = 256 + 8;       // staged gradient row: 256 pixels + pad (BF16)
 constexpr int WT_TILES = 5 * WT_GROUPS + 1;  // column tiles per workgroup (+ bias)
 
-template <int MT>
+template <int MT, bool XF32>
 __global__ void __launch_bounds__(CT) k_wgrad_tile(WgradArgs A) {
+  constexpr int NGI = (128 * MT * 4 + CT - 1) / CT;         // gradient items per thread
+  constexpr int NXI = (WT_GROUPS * 18 * 18 + CT - 1) / CT;  // input items per thread
   static_assert(MT * WT_TILES * 64 * 4 * 4 <= WT_GROUPS * 3 * 8 * 18 * 16 * 2, "reduction fits the patch LDS");
   __shared__ __align__(16) uint16_t s_g[MT * 16][WT_PITCH];
   __shared__ __align__(16) uint16_t s_x[WT_GROUPS][3][8][18][16];
@@ -532,39 +543,94 @@ __global__ void __launch_bounds__(CT) k_wgrad_tile(WgradArgs A) {
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int b = tile / per_img, tt = tile - b * per_img;
     const int ty0 = (tt / tiles_x) * 16, tx0 = (tt % tiles_x) * 16;
-    // gradient, transposed: thread = (pixel pair of a row, 4 channels)
-    for (int e = tid; e < 128 * MT * 4; e += CT) {
+    // Every load of the tile is issued before any LDS write, so the tile
+    // costs one memory round trip: gradient items (a pixel pair of a row, 4
+    // channels) and input items (one pixel of one 8-channel group, 16 bytes,
+    // 32 for an FP32 part, rounded when written).
+    uint2 gv[NGI][2];
+#pragma unroll
+    for (int i = 0; i < NGI; ++i) {
+      const int e = tid + CT * i;
+      gv[i][0] = make_uint2(0u, 0u);
+      gv[i][1] = make_uint2(0u, 0u);
       const int pp = e & 127, cq = e >> 7;
       const int r = pp >> 3, c = 2 * (pp & 7);
-      uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
       const int oy = ty0 + r, ox = tx0 + c;
-      if (4 * cq < A.cout && oy < A.Ho) {
+      if (e < 128 * MT * 4 && 4 * cq < A.cout && oy < A.Ho) {
         const int64_t o = (((int64_t)b * A.Ho + oy) * A.Wo + ox) * A.d_stride + 4 * cq;
-        if (ox < A.Wo) v0 = *reinterpret_cast<const uint2*>(A.g_bf16 + o);
-        if (ox + 1 < A.Wo) v1 = *reinterpret_cast<const uint2*>(A.g_bf16 + o + A.d_stride);
+        if (ox < A.Wo) gv[i][0] = *reinterpret_cast<const uint2*>(A.g_bf16 + o);
+        if (ox + 1 < A.Wo) gv[i][1] = *reinterpret_cast<const uint2*>(A.g_bf16 + o + A.d_stride);
       }
-      uint32_t* row = reinterpret_cast<uint32_t*>(&s_g[4 * cq][r * 16 + c]);
-      row[0 * WT_PITCH / 2] = (v0.x & 0xFFFFu) | (v1.x << 16);
-      row[1 * WT_PITCH / 2] = (v0.x >> 16) | (v1.x & 0xFFFF0000u);
-      row[2 * WT_PITCH / 2] = (v0.y & 0xFFFFu) | (v1.y << 16);
-      row[3 * WT_PITCH / 2] = (v0.y >> 16) | (v1.y & 0xFFFF0000u);
+    }
+    uint32_t xv[NXI][8];
+#pragma unroll
+    for (int i = 0; i < NXI; ++i) {
+      const int e = tid + CT * i;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) xv[i][k] = 0u;
+      if (e < ngr * 18 * 18) {
+        const int gi = e / 324, pix = e - gi * 324;
+        const int pr = pix / 18, pc = pix - pr * 18;
+        const int g8 = gbase + gi;
+        const bool in_a = 8 * g8 < A.src.a.c;
+        const PartR part = part_pick(in_a, A.src.a, A.src.b);
+        const int64_t o = wm_offset8(part, b, A.y0 + ty0 + pr - 1, A.x0 + tx0 + pc - 1,
+                                     in_a ? 8 * g8 : 8 * g8 - A.src.a.c, A.H, A.W);
+        if (o >= 0) {
+          // one address for both kinds: 16 bytes, and 16 more for FP32
+          const bool f32 = XF32 && part.f32 != nullptr;
+          const uint4* q = reinterpret_cast<const uint4*>(
+              (f32 ? reinterpret_cast<const char*>(part.f32) : reinterpret_cast<const char*>(part.bf16)) +
+              o * (f32 ? 4 : 2));
+          // (a BF16 part reads its 16 bytes twice: no branch, so nothing
+          // that uses the data is moved up between the loads)
+          const uint4 q0 = q[0], q1 = *(f32 ? q + 1 : q);
+          xv[i][0] = q0.x;
+          xv[i][1] = q0.y;
+          xv[i][2] = q0.z;
+          xv[i][3] = q0.w;
+          xv[i][4] = q1.x;
+          xv[i][5] = q1.y;
+          xv[i][6] = q1.z;
+          xv[i][7] = q1.w;
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NGI; ++i) {
+      const int e = tid + CT * i;
+      if (e < 128 * MT * 4) {
+        const int pp = e & 127, cq = e >> 7;
+        const int r = pp >> 3, c = 2 * (pp & 7);
+        const uint2 v0 = gv[i][0], v1 = gv[i][1];
+        uint32_t* row = reinterpret_cast<uint32_t*>(&s_g[4 * cq][r * 16 + c]);
+        row[0 * WT_PITCH / 2] = (v0.x & 0xFFFFu) | (v1.x << 16);
+        row[1 * WT_PITCH / 2] = (v0.x >> 16) | (v1.x & 0xFFFF0000u);
+        row[2 * WT_PITCH / 2] = (v0.y & 0xFFFFu) | (v1.y << 16);
+        row[3 * WT_PITCH / 2] = (v0.y >> 16) | (v1.y & 0xFFFF0000u);
+      }
     }
     // input patch of each group in its three shifted copies
-    for (int e = tid; e < ngr * 18 * 18; e += CT) {
-      const int gi = e / 324, pix = e - gi * 324;
-      const int pr = pix / 18, pc = pix - pr * 18;
-      const int g8 = gbase + gi;
-      const bool in_a = 8 * g8 < A.src.a.c;
-      const uint4 v = wm_load8(part_pick(in_a, A.src.a, A.src.b), b, A.y0 + ty0 + pr - 1, A.x0 + tx0 + pc - 1,
-                               in_a ? 8 * g8 : 8 * g8 - A.src.a.c, A.H, A.W);
-      const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-      for (int kx = 0; kx < 3; ++kx) {
-        const int col = pc - kx;
-        if (col < 0 || col >= 16) continue;
+    for (int i = 0; i < NXI; ++i) {
+      const int e = tid + CT * i;
+      if (e < ngr * 18 * 18) {
+        const int gi = e / 324, pix = e - gi * 324;
+        const int pr = pix / 18, pc = pix - pr * 18;
+        const int g8 = gbase + gi;
+        const bool f32 = XF32 && (8 * g8 < A.src.a.c ? A.src.a.f32 : A.src.b.f32) != nullptr;
+        uint32_t w4[4];
 #pragma unroll
-        for (int ci = 0; ci < 8; ++ci)
-          s_x[gi][kx][ci][pr][col] = (uint16_t)((ci & 1) ? (w4[ci >> 1] >> 16) : (w4[ci >> 1] & 0xFFFFu));
+        for (int k = 0; k < 4; ++k)
+          w4[k] = f32 ? wm_pack(__uint_as_float(xv[i][2 * k]), __uint_as_float(xv[i][2 * k + 1])) : xv[i][k];
+#pragma unroll
+        for (int kx = 0; kx < 3; ++kx) {
+          const int col = pc - kx;
+          if (col < 0 || col >= 16) continue;
+#pragma unroll
+          for (int ci = 0; ci < 8; ++ci)
+            s_x[gi][kx][ci][pr][col] = (uint16_t)((ci & 1) ? (w4[ci >> 1] >> 16) : (w4[ci >> 1] & 0xFFFFu));
+        }
       }
     }
     __syncthreads();
@@ -803,10 +869,19 @@ int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st) {
   if (a.mfma == 2 && a.g_bf16 && a.src.a.c % 8 == 0 && a.src.b.c % 8 == 0 && a.cout <= 32 && a.d_stride % 4 == 0) {
     const int ng8 = cin / 8;
     dim3 grid((unsigned)a.nchunk, (unsigned)((ng8 + WT_GROUPS - 1) / WT_GROUPS));
-    if (a.cout <= 16)
-      hipLaunchKernelGGL(k_wgrad_tile<1>, grid, dim3(CT), 0, st, a);
-    else
-      hipLaunchKernelGGL(k_wgrad_tile<2>, grid, dim3(CT), 0, st, a);
+    // an FP32-stored part needs the rounding at staging, compiled in only where used
+    const bool xf32 = (a.src.a.c > 0 && a.src.a.f32) || (a.src.b.c > 0 && a.src.b.f32);
+    if (a.cout <= 16) {
+      if (xf32)
+        hipLaunchKernelGGL((k_wgrad_tile<1, true>), grid, dim3(CT), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_wgrad_tile<1, false>), grid, dim3(CT), 0, st, a);
+    } else {
+      if (xf32)
+        hipLaunchKernelGGL((k_wgrad_tile<2, true>), grid, dim3(CT), 0, st, a);
+      else
+        hipLaunchKernelGGL((k_wgrad_tile<2, false>), grid, dim3(CT), 0, st, a);
+    }
   } else if (a.mfma && a.g_bf16 && a.src.a.c % 8 == 0 && a.src.b.c % 8 == 0) {
     // the matrix-core kernel stages 8 channels of one part at a time
     // column tiles per wave: the fewest that cover the columns in one

@@ -725,6 +725,12 @@ __global__ void k_pack_weights_bf16(const uint16_t* __restrict__ w, uint16_t* __
   }
 }
 
+// 8 values per thread: two 16-byte loads, one 16-byte store
+__global__ void k_round8_bf16(const float* __restrict__ w, uint16_t* __restrict__ out, int64_t n8) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n8) *reinterpret_cast<u16x8*>(out + 8 * i) = f32x8_to_bf16(w + 8 * i);
+}
+
 __global__ void k_round_bf16(const float* __restrict__ w, uint16_t* __restrict__ out, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] = f2bf(w[i]);
@@ -977,7 +983,12 @@ size_t ls_bf16_packed_offset(int l) {
 size_t ls_bf16_packed_total() { return ls_bf16_packed_offset(LS_NLAYER); }
 
 int ls_pack_bf16(const float* w, uint16_t* out, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_round_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, out, n);
+  if (n % 8 == 0 && (reinterpret_cast<uintptr_t>(w) % 16) == 0 && (reinterpret_cast<uintptr_t>(out) % 16) == 0) {
+    const int64_t n8 = n / 8;
+    hipLaunchKernelGGL(k_round8_bf16, dim3((unsigned)((n8 + 255) / 256)), dim3(256), 0, st, w, out, n8);
+  } else {
+    hipLaunchKernelGGL(k_round_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, w, out, n);
+  }
   LS_LAUNCH_CHECK();
   return LS_OK;
 }
@@ -1254,6 +1265,7 @@ __global__ void __launch_bounds__(256, MINW) k_conv2_bf16(Conv2Args A) {
   constexpr int KPAD1 = (9 * CIN1 + 31) / 32 * 32, KPAD2 = (9 * CIN2 + 31) / 32 * 32;
   constexpr int WP1 = wpitch_c(KPAD1), WP2 = wpitch_c(KPAD2);
   constexpr int NU1 = PT * PT * (CIN1 / 8), NJ1 = (NU1 + 255) / 256, RW1 = F32A ? 8 : 4;
+  constexpr int C82 = CB2 > 0 ? CB2 / 8 : 1;  // 8-channel units per pixel of the second part
   constexpr int NU2 = PT * PT * (CB2 / 8), NJ2 = CB2 > 0 ? (NU2 + 255) / 256 : 0, RW2 = F32B ? 8 : 4;
   __shared__ __align__(16) uint16_t s1[PT * PT * P1];
   __shared__ __align__(16) uint16_t s2[PT * PT * P2];
@@ -1325,7 +1337,7 @@ __global__ void __launch_bounds__(256, MINW) k_conv2_bf16(Conv2Args A) {
 #pragma unroll
       for (int r = 0; r < RW2; ++r) pf2[j][r] = 0u;
       const int u = threadIdx.x + 256 * j;
-      if (u < NU2) fetch_part(A.b2, b, oy0 - 1, ox0 - 1, u, CB2 / 8, F32B, pf2[j]);
+      if (u < NU2) fetch_part(A.b2, b, oy0 - 1, ox0 - 1, u, C82, F32B, pf2[j]);
     }
   };
   auto to_lds = [&](const uint32_t* r, bool f32, uint16_t* dst) {
@@ -1368,7 +1380,7 @@ __global__ void __launch_bounds__(256, MINW) k_conv2_bf16(Conv2Args A) {
     for (int j = 0; j < NJ2; ++j) {
       const int u = threadIdx.x + 256 * j;
       if (u < NU2) {
-        const int pix = u / (CB2 / 8), ch = u - pix * (CB2 / 8);
+        const int pix = u / C82, ch = u - pix * C82;
         to_lds(pf2[j], F32B, s2 + pix * P2 + 16 + 8 * ch);
       }
     }
