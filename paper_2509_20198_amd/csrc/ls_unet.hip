@@ -358,7 +358,7 @@ __device__ __forceinline__ uint4 wm_load8(const PartR& p, int b, int yy, int xx,
   return make_uint4(wm_pack(f0.x, f0.y), wm_pack(f0.z, f0.w), wm_pack(f1.x, f1.y), wm_pack(f1.z, f1.w));
 }
 
-template <int MT, int CTW>
+template <int MT, int CTW, bool XF32>
 __global__ void __launch_bounds__(CT) k_wgrad_mfma(WgradArgs A) {
   constexpr int COLS = 4 * CTW * 16;
   constexpr int NJ = COLS / 128;  // column octets a thread stages per slab
@@ -405,46 +405,86 @@ __global__ void __launch_bounds__(CT) k_wgrad_mfma(WgradArgs A) {
 #pragma unroll
     for (int ct = 0; ct < CTW; ++ct) acc[mt][ct] = wm_f32x4{0.f, 0.f, 0.f, 0.f};
   for (int64_t ps = p0; ps < p1; ps += 32) {
-    // gradient: thread = (pixel pair, 4 channels)
-    for (int e = tid; e < 16 * MT * 4; e += CT) {
-      const int cq = e >> 4;
-      uint2 v0 = make_uint2(0u, 0u), v1 = make_uint2(0u, 0u);
-      if (4 * cq < A.cout) {
+    // all loads of the slab first (gradient: thread = (pixel pair, 4
+    // channels); im2col: thread = (pixel pair, 8 columns of one tap)), then
+    // the LDS writes, so the slab costs one memory round trip
+    constexpr int NGE = (16 * MT * 4 + CT - 1) / CT;
+    uint2 gv[NGE][2];
+#pragma unroll
+    for (int i = 0; i < NGE; ++i) {
+      const int e = tid + CT * i, cq = e >> 4;
+      gv[i][0] = make_uint2(0u, 0u);
+      gv[i][1] = make_uint2(0u, 0u);
+      if (e < 16 * MT * 4 && 4 * cq < A.cout) {
         const int64_t pa = ps + 2 * pp;
-        if (pa < p1) v0 = *reinterpret_cast<const uint2*>(A.g_bf16 + pa * A.d_stride + 4 * cq);
-        if (pa + 1 < p1) v1 = *reinterpret_cast<const uint2*>(A.g_bf16 + (pa + 1) * A.d_stride + 4 * cq);
+        if (pa < p1) gv[i][0] = *reinterpret_cast<const uint2*>(A.g_bf16 + pa * A.d_stride + 4 * cq);
+        if (pa + 1 < p1) gv[i][1] = *reinterpret_cast<const uint2*>(A.g_bf16 + (pa + 1) * A.d_stride + 4 * cq);
       }
-      uint32_t* row = reinterpret_cast<uint32_t*>(&s_g[4 * cq][2 * pp]);
-      row[0 * WM_PITCH / 2] = (v0.x & 0xFFFFu) | (v1.x << 16);
-      row[1 * WM_PITCH / 2] = (v0.x >> 16) | (v1.x & 0xFFFF0000u);
-      row[2 * WM_PITCH / 2] = (v0.y & 0xFFFFu) | (v1.y << 16);
-      row[3 * WM_PITCH / 2] = (v0.y >> 16) | (v1.y & 0xFFFF0000u);
     }
-    // im2col columns: thread = (pixel pair, 8 columns of one tap)
+    uint32_t xv[NJ][2][8];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int d = cdesc[j], kind = d >> 24;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) xv[j][h][k] = 0u;
+        if (ps + 2 * pp + h < p1) {
+          if (kind < 2) {
+            const int ky = (d >> 20) & 3, kx = (d >> 18) & 3, cc = d & 0x3FFFF;
+            const PartR part = part_pick(kind == 0, A.src.a, A.src.b);
+            const int64_t o = wm_offset8(part, pb[h], A.y0 + py[h] + ky - 1, A.x0 + px[h] + kx - 1, cc, A.H, A.W);
+            if (o >= 0) {
+              // one address for both kinds (a BF16 part reads its 16 bytes twice)
+              const bool f32 = XF32 && part.f32 != nullptr;
+              const uint4* q = reinterpret_cast<const uint4*>(
+                  (f32 ? reinterpret_cast<const char*>(part.f32) : reinterpret_cast<const char*>(part.bf16)) +
+                  o * (f32 ? 4 : 2));
+              const uint4 q0 = q[0], q1 = XF32 ? *(f32 ? q + 1 : q) : q0;
+              xv[j][h][0] = q0.x;
+              xv[j][h][1] = q0.y;
+              xv[j][h][2] = q0.z;
+              xv[j][h][3] = q0.w;
+              xv[j][h][4] = q1.x;
+              xv[j][h][5] = q1.y;
+              xv[j][h][6] = q1.z;
+              xv[j][h][7] = q1.w;
+            }
+          } else if (kind == 2) {
+            xv[j][h][0] = 0x3F80u;  // BF16 1.0 in column N
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NGE; ++i) {
+      const int e = tid + CT * i, cq = e >> 4;
+      if (e < 16 * MT * 4) {
+        const uint2 v0 = gv[i][0], v1 = gv[i][1];
+        uint32_t* row = reinterpret_cast<uint32_t*>(&s_g[4 * cq][2 * pp]);
+        row[0 * WM_PITCH / 2] = (v0.x & 0xFFFFu) | (v1.x << 16);
+        row[1 * WM_PITCH / 2] = (v0.x >> 16) | (v1.x & 0xFFFF0000u);
+        row[2 * WM_PITCH / 2] = (v0.y & 0xFFFFu) | (v1.y << 16);
+        row[3 * WM_PITCH / 2] = (v0.y >> 16) | (v1.y & 0xFFFF0000u);
+      }
+    }
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       const int co8 = (tid >> 4) + 16 * j;
       const int d = cdesc[j], kind = d >> 24;
-      uint4 v[2];
+      uint32_t a[2][4];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        v[h] = make_uint4(0u, 0u, 0u, 0u);
-        if (ps + 2 * pp + h < p1) {
-          if (kind < 2) {
-            const int ky = (d >> 20) & 3, kx = (d >> 18) & 3, cc = d & 0x3FFFF;
-            v[h] = wm_load8(part_pick(kind == 0, A.src.a, A.src.b), pb[h], A.y0 + py[h] + ky - 1, A.x0 + px[h] + kx - 1, cc,
-                            A.H, A.W);
-          } else if (kind == 2) {
-            v[h].x = 0x3F80u;  // BF16 1.0 in column N
-          }
-        }
+        const bool f32 = XF32 && kind < 2 && (kind == 0 ? A.src.a.f32 : A.src.b.f32) != nullptr;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          a[h][k] = f32 ? wm_pack(__uint_as_float(xv[j][h][2 * k]), __uint_as_float(xv[j][h][2 * k + 1])) : xv[j][h][k];
       }
       uint32_t* row = reinterpret_cast<uint32_t*>(&s_x[8 * co8][2 * pp]);
-      const uint32_t a0[4] = {v[0].x, v[0].y, v[0].z, v[0].w}, a1[4] = {v[1].x, v[1].y, v[1].z, v[1].w};
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        row[(2 * c) * WM_PITCH / 2] = (a0[c] & 0xFFFFu) | (a1[c] << 16);
-        row[(2 * c + 1) * WM_PITCH / 2] = (a0[c] >> 16) | (a1[c] & 0xFFFF0000u);
+        row[(2 * c) * WM_PITCH / 2] = (a[0][c] & 0xFFFFu) | (a[1][c] << 16);
+        row[(2 * c + 1) * WM_PITCH / 2] = (a[0][c] >> 16) | (a[1][c] & 0xFFFF0000u);
       }
     }
     __syncthreads();
@@ -889,7 +929,14 @@ int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st) {
     const int tiles = (9 * cin + 1 + 15) / 16;
     const int ctw = tiles <= 8 ? 2 : (tiles <= 16 ? 4 : 8);
     dim3 grid((unsigned)((9 * cin + 1 + 64 * ctw - 1) / (64 * ctw)), (unsigned)a.nchunk);
-#define LS_WM(M, C) hipLaunchKernelGGL((k_wgrad_mfma<M, C>), grid, dim3(CT), 0, st, a)
+    const bool xf32 = (a.src.a.c > 0 && a.src.a.f32) || (a.src.b.c > 0 && a.src.b.f32);
+#define LS_WM(M, C)                                                            \
+  do {                                                                         \
+    if (xf32)                                                                  \
+      hipLaunchKernelGGL((k_wgrad_mfma<M, C, true>), grid, dim3(CT), 0, st, a);  \
+    else                                                                       \
+      hipLaunchKernelGGL((k_wgrad_mfma<M, C, false>), grid, dim3(CT), 0, st, a); \
+  } while (0)
     const int mt = (a.cout + 15) / 16;
     if (mt == 1) {
       if (ctw == 2) LS_WM(1, 2); else if (ctw == 4) LS_WM(1, 4); else LS_WM(1, 8);
