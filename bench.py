@@ -63,11 +63,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def unet_flops(res: int, pad: int) -> float:
+def unet_flops(res: int, pad: int, inference: bool = True) -> float:
     """Multiply-add FLOPs (x2) of one tile's forward: every 3x3 conv on its
-    plane, the head only on the res x res crop."""
+    plane, the head only on the res x res crop; for inference dec1a and
+    dec1b only on the crop grown by the two and one texels the layers after
+    them read (training keeps their whole planes for the backward)."""
     R = res + 2 * pad
     planes = [R, R, R // 2, R // 2, R // 4, R // 4, R // 2, R // 2, R, R]
+    if inference:
+        planes[8] = min(R, res + 4)
+        planes[9] = min(R, res + 2)
     total = 0
     for (name, ci, co), hw in zip(synth.UNET_SHAPES[:-1], planes):
         total += 2 * hw * hw * co * 9 * ci
@@ -515,7 +520,7 @@ def bench_training(dev, train_steps: int = 60):
 
         ms = Timer().run(step, 5, 2)
         ms_rc = Timer().run(step_recompute, 5, 2)
-        flops = 3 * unet_flops(g.res, g.pad) * nt  # forward + input gradient + weight gradient
+        flops = 3 * unet_flops(g.res, g.pad, inference=False) * nt  # forward + input gradient + weight gradient
         out[name] = {"fwd_bwd_ms": ms, "tiles_per_s": nt / (ms * 1e-3), "fwd_bwd_recompute_ms": ms_rc,
                      "achieved_TFLOPs": flops / (ms * 1e-3) / 1e12,
                      "frac_peak": flops / (ms * 1e-3) / 1e12 / (PEAK_BF16_TFLOPS if prec == ls.BF16
@@ -695,15 +700,21 @@ def bench_stream(dev, splat_points: int = 500_000_000, splat_tiles: int = 256):
 def lsnet_flops(res: int, pad: int) -> float:
     """Multiply-add FLOPs (x2) of one tile through the paper's network as the
     library runs it (the first encoder layers as one 8 -> 64 conv, the FC1
-    pair as one GEMM with its zero blocks, the last layer on the crop)."""
+    pair as one GEMM with its zero blocks; the decoders' last layer and the
+    final CNN only on the crop grown by the halo the layers after them read:
+    3, 2, 1 and 0 texels)."""
     R = res + 2 * pad
+
+    def win(halo):
+        return min(R, res + 2 * halo) ** 2
+
     L = (R // 16) ** 2 * 32
     f = 2 * R * R * 64 * 9 * 8
     f += 4 * 2 * (R // 2) ** 2 * 32 * 9 * 16 + 4 * 2 * (R // 4) ** 2 * 32 * 9 * 32 + 4 * 2 * (R // 8) ** 2 * 32 * 9 * 32
     f += 2 * 512 * 4 * L + 2 * 2 * L * 512
     f += 2 * (2 * (R // 8) ** 2 * 32 * 9 * 32 + 2 * (R // 4) ** 2 * 32 * 9 * 32 + 2 * (R // 2) ** 2 * 16 * 9 * 32
-              + 2 * R * R * 16 * 9 * 16)
-    f += 2 * R * R * 32 * 9 * 40 + 2 * R * R * 32 * 9 * 32 + 2 * res * res * 4 * 9 * 32
+              + 2 * win(3) * 16 * 9 * 16)
+    f += 2 * win(2) * 32 * 9 * 40 + 2 * win(1) * 32 * 9 * 32 + 2 * win(0) * 4 * 9 * 32
     return float(f)
 
 

@@ -592,6 +592,23 @@ int conv16(const ConvSrc& s, int B, int H, const uint16_t* wp, int kpad, const f
   return ls_bf16_conv_pipe(a, nt, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr, f32b, st);
 }
 
+// A square window [y0, y0 + n) of the plane (both axes): the part of a
+// full-resolution layer's output that the layers after it read, here the
+// crop grown by `halo` texels and clipped to the plane.
+struct Window {
+  int y0, n;
+};
+Window crop_window(int R, int pad, int res, int halo) {
+  const int a = std::max(0, pad - halo), b = std::min(R, pad + res + halo);
+  return Window{a, b - a};
+}
+// a tensor stored for a window only, read as part of the plane
+SrcPart window_part(SrcPart p, const Window& w) {
+  p.oy = w.y0;
+  p.ox = w.y0;
+  return p;
+}
+
 ConvSrc src1(SrcPart a) {
   ConvSrc s;
   s.a = a;
@@ -652,6 +669,9 @@ int ls_lsnet_forward_impl(const float* w, int precision, int inputs, const float
     LS_LAUNCH_CHECK();
   }
   const int R2 = R / 2, R4 = R / 4, R8 = R / 8, R16 = R / 16;
+  // windows of the final CNN's inputs: fin3 reads fin2 on the crop + 1,
+  // fin2 reads fin1 on the crop + 2, fin1 reads the decoders on the crop + 3
+  const Window w2 = crop_window(R, pad, res, 1), w1 = crop_window(R, pad, res, 2), wa = crop_window(R, pad, res, 3);
   const int64_t L = net.L;
   const double r_m = (double)gi.H * gi.scale_xy;
   for (int t0 = 0; t0 < n_tiles; t0 += chunk) {
@@ -698,17 +718,18 @@ int ls_lsnet_forward_impl(const float* w, int precision, int inputs, const float
         LS_TRYN(conv32(src1(part_f32(Dd2, 32, R4, 64, 32 * k, true)), B, R2, wf + d.conv_t[l0 + 2],
                        w + net.boff[l0 + 2], 16, 1, Dd3, 32, 16 * k, 0, 0, R2, st));
         LS_TRYN(conv32(src1(part_f32(Dd3, 16, R2, 32, 16 * k, true)), B, R, wf + d.conv_t[l0 + 3],
-                       w + net.boff[l0 + 3], 16, 1, Aht, 32, 16 * k, 0, 0, R, st));
+                       w + net.boff[l0 + 3], 16, 1, Aht, 32, 16 * k, wa.y0, wa.y0, wa.n, st));
       }
-      // final CNN over [a_h, a_t, x], the last layer on the crop only
+      // final CNN over [a_h, a_t, x], the last layer on the crop only (and
+      // each earlier layer only where the next one reads it)
       ConvSrc s1;
-      s1.a = part_f32(Aht, 32, R, 32, 0, false);
+      s1.a = window_part(part_f32(Aht, 32, wa.n, 32, 0, false), wa);
       s1.b = X;
-      LS_TRYN(conv32(s1, B, R, wf + d.conv_t[L_FIN1], w + net.boff[L_FIN1], 32, 1, F1, 32, 0, 0, 0, R, st));
-      LS_TRYN(conv32(src1(part_f32(F1, 32, R, 32, 0, false)), B, R, wf + d.conv_t[L_FIN2], w + net.boff[L_FIN2], 32,
-                     1, F2, 32, 0, 0, 0, R, st));
-      LS_TRYN(conv32(src1(part_f32(F2, 32, R, 32, 0, false)), B, R, wf + d.conv_t[L_FIN3], w + net.boff[L_FIN3], 4,
-                     0, head, 4, 0, pad, pad, res, st));
+      LS_TRYN(conv32(s1, B, R, wf + d.conv_t[L_FIN1], w + net.boff[L_FIN1], 32, 1, F1, 32, 0, w1.y0, w1.y0, w1.n, st));
+      LS_TRYN(conv32(src1(window_part(part_f32(F1, 32, w1.n, 32, 0, false), w1)), B, R, wf + d.conv_t[L_FIN2],
+                     w + net.boff[L_FIN2], 32, 1, F2, 32, 0, w2.y0, w2.y0, w2.n, st));
+      LS_TRYN(conv32(src1(window_part(part_f32(F2, 32, w2.n, 32, 0, false), w2)), B, R, wf + d.conv_t[L_FIN3],
+                     w + net.boff[L_FIN3], 4, 0, head, 4, 0, pad, pad, res, st));
     } else {
       uint16_t* A0 = act16;
       auto P = [&](int64_t off) { return A0 + off * B; };
@@ -746,18 +767,20 @@ int ls_lsnet_forward_impl(const float* w, int precision, int inputs, const float
                        d.kpad[l0 + 2], w + net.boff[l0 + 2], 16, 1, Dd3, 32, 16 * k, nullptr, 0, 0, nullptr, 0, 0,
                        R2, st));
         LS_TRYN(conv16(src1(part_bf16(Dd3, 16, R2, 32, 16 * k, true)), B, R, wb + d.conv_p[l0 + 3],
-                       d.kpad[l0 + 3], w + net.boff[l0 + 3], 16, 1, Aht, 32, 16 * k, nullptr, 0, 0, nullptr, 0, 0, R,
-                       st));
+                       d.kpad[l0 + 3], w + net.boff[l0 + 3], 16, 1, Aht, 32, 16 * k, nullptr, 0, 0, nullptr, wa.y0,
+                       wa.y0, wa.n, st));
       }
       ConvSrc s1;
-      s1.a = part_bf16(Aht, 32, R, 32, 0, false);
+      s1.a = window_part(part_bf16(Aht, 32, wa.n, 32, 0, false), wa);
       s1.b = X;
       LS_TRYN(conv16(s1, B, R, wb + d.conv_p[L_FIN1], d.kpad[L_FIN1], w + net.boff[L_FIN1], 32, 1, F1, 32, 0, nullptr,
-                     0, 0, nullptr, 0, 0, R, st));
-      LS_TRYN(conv16(src1(part_bf16(F1, 32, R, 32, 0, false)), B, R, wb + d.conv_p[L_FIN2], d.kpad[L_FIN2],
-                     w + net.boff[L_FIN2], 32, 1, F2, 32, 0, nullptr, 0, 0, nullptr, 0, 0, R, st));
-      LS_TRYN(conv16(src1(part_bf16(F2, 32, R, 32, 0, false)), B, R, wb + d.conv_p[L_FIN3], d.kpad[L_FIN3],
-                     w + net.boff[L_FIN3], 4, 0, nullptr, 4, 0, nullptr, 0, 0, head, pad, pad, res, st));
+                     0, 0, nullptr, w1.y0, w1.y0, w1.n, st));
+      LS_TRYN(conv16(src1(window_part(part_bf16(F1, 32, w1.n, 32, 0, false), w1)), B, R, wb + d.conv_p[L_FIN2],
+                     d.kpad[L_FIN2], w + net.boff[L_FIN2], 32, 1, F2, 32, 0, nullptr, 0, 0, nullptr, w2.y0, w2.y0,
+                     w2.n, st));
+      LS_TRYN(conv16(src1(window_part(part_bf16(F2, 32, w2.n, 32, 0, false), w2)), B, R, wb + d.conv_p[L_FIN3],
+                     d.kpad[L_FIN3], w + net.boff[L_FIN3], 4, 0, nullptr, 4, 0, nullptr, 0, 0, head, pad, pad, res,
+                     st));
     }
     {
       const int64_t ne = (int64_t)B * res * res;
