@@ -18,7 +18,10 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# LS_ORACLE_LIB loads another, already built copy of the same sources (the
+# sanitizer build that a test makes with build_sanitized); nothing rebuilds it
+_LIB_ENV = os.environ.get("LS_ORACLE_LIB")
+_LIB_PATH = _LIB_ENV or os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["ora_recon.c", "ora_unet.c", "ora_splat.c", "ora_target.c", "ora_raster.c", "ora_pnet.c"]
 _lock = threading.Lock()
 _lib = None
@@ -38,6 +41,17 @@ def build(force: bool = True) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized(path: str) -> str:
+    """The same sources with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every finding fatal), for tests that run the oracle under them."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    cmd = ["gcc", "-O1", "-g", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-o", path] + srcs
+    subprocess.run(cmd, check=True)
+    return path
 
 
 class _Grid(ctypes.Structure):
@@ -60,7 +74,8 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build(force=False)
+            if not _LIB_ENV:
+                build(force=False)
             lib = ctypes.CDLL(_LIB_PATH)
             P = ctypes.c_void_p
             i32, i64, u64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
