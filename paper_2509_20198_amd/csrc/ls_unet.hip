@@ -747,7 +747,7 @@ __global__ void __launch_bounds__(CT) k_wgrad_tile(WgradArgs A) {
   }
 }
 
-constexpr int RED_OUT = 16, RED_SEG = CT / RED_OUT;
+constexpr int RED_OUT = 16, RED_SEG = CT / RED_OUT, RED_BATCH = 16;
 __global__ void __launch_bounds__(CT) k_reduce_partials(const float* __restrict__ partial, int nchunk, int64_t n,
                                                       float* __restrict__ out) {
   __shared__ float s_run[RED_SEG][RED_OUT];
@@ -756,8 +756,22 @@ __global__ void __launch_bounds__(CT) k_reduce_partials(const float* __restrict_
   const int len = (nchunk + RED_SEG - 1) / RED_SEG;
   const int c0 = seg * len, c1 = min(nchunk, c0 + len);
   float s = 0.f;
-  if (i < n)
-    for (int c = c0; c < c1; ++c) s += partial[(int64_t)c * n + i];
+  if (i < n) {
+    // the run's values are loaded RED_BATCH at a time before they are added
+    // (in chunk order, as a plain loop would), so a run costs about one
+    // memory round trip per batch instead of one per chunk
+    const float* p = partial + (int64_t)c0 * n + i;
+    const int cnt = c1 - c0;
+    int c = 0;
+    for (; c + RED_BATCH <= cnt; c += RED_BATCH) {
+      float v[RED_BATCH];
+#pragma unroll
+      for (int j = 0; j < RED_BATCH; ++j) v[j] = p[(int64_t)(c + j) * n];
+#pragma unroll
+      for (int j = 0; j < RED_BATCH; ++j) s += v[j];
+    }
+    for (; c < cnt; ++c) s += p[(int64_t)c * n];
+  }
   s_run[seg][o] = s;
   __syncthreads();
   if (seg == 0 && i < n) {
