@@ -218,7 +218,11 @@ int wgrad_bf16(const ConvSrc& s, int B, int H, int l, const uint16_t* g, int d_s
   const bool tile_ok = a.cout <= 32;
   a.mfma = cfg < 0 ? (tile_ok ? 2 : 1) : (cfg >= 6 ? (tile_ok ? 2 : 1) : (cfg >= 3 ? 1 : 0));
   const int64_t npix = (int64_t)B * Ho * Wo;
-  const int chunks = ls_wgrad_chunks_for_config(cfg);
+  // default: 512 pixel chunks, 256 for layers with many weights on planes
+  // below about 1.5 M pixels (measured on 256 tiles: there the partial sums,
+  // 4 bytes per weight and chunk, cost more than the parallelism gains)
+  const int64_t nw = (int64_t)a.cout * 9 * (s.a.c + s.b.c);
+  const int chunks = cfg >= 0 ? ls_wgrad_chunks_for_config(cfg) : (npix < ((int64_t)3 << 19) && nw >= 6000 ? 256 : 512);
   a.nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(chunks, npix / 256));
   return ls_wgrad_f32(a, grad_w + ls_layer_w_offset(l), st);
 }
