@@ -199,6 +199,29 @@ def cpu_baseline(work, sample_idx, gpu_tex_bf16, gpu_tex_fp32, weights64):
     }
 
 
+def binning_rate(region, x, y, stage_ms: dict) -> dict:
+    """Tile binning throughput: each sparse point's x, y read once (8 B) and
+    one 4-byte point index written per window that holds it (a window is its
+    tile grown by `pad` texels; every tile of the region is listed)."""
+    ms = sum(stage_ms.get(k) or 0.0 for k in ("bin_count", "bin_scan", "bin_scatter"))
+    if ms <= 0:
+        return {}
+    S, P = region.tile_size, region.pad * region.cell
+    xs = x.detach().cpu().numpy().astype(np.int64) - region.origin_x
+    ys = y.detach().cpu().numpy().astype(np.int64) - region.origin_y
+
+    def windows(v, ntile):
+        t, r = v // S, v % S
+        return 1 + ((r < P) & (t > 0)) + ((r >= S - P) & (t < ntile - 1))
+
+    member = int((windows(xs, region.tiles_x) * windows(ys, region.tiles_y)).sum())
+    nbytes = 8 * xs.size + 4 * member
+    return {"ms": ms, "points": int(xs.size), "memberships": member, "points_per_s": xs.size / (ms * 1e-3),
+            "algorithmic_GBps": nbytes / (ms * 1e-3) / 1e9, "frac_hbm_peak": nbytes / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "algorithmic_bytes": "8 B per point (x, y) + 4 B per point and window holding it",
+            "kernels": "bin_count + bin_scan + bin_scatter"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -312,7 +335,7 @@ def main():
     if dom == "conv_bf16":
         ms_dom = kernels[dom]["ms_per_step"]
         ach = flops_tile * nt / (ms_dom * 1e-3) / 1e12
-        roof = {"kernel": "conv_bf16 (all 11 conv launches of a step)", "bound": "mfma", "achieved": ach,
+        roof = {"kernel": "conv_bf16 (every conv launch of a step)", "bound": "mfma", "achieved": ach,
                 "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_BF16_TFLOPS, "traffic": None,
                 "avg_launch_ms": ms_dom / kernels[dom]["launches_per_step"],
                 "algorithmic_per_step": f"{flops_tile * nt / 1e9:.1f} GFLOP ({flops_tile / 1e9:.4f} GFLOP/tile)"}
@@ -332,7 +355,7 @@ def main():
     conv_tf = flops_tile * nt / (conv_ms * 1e-3) / 1e12 if conv_ms > 0 else None
     conv_bytes = unet_bytes(res, g.pad) * nt
     conv_gbs = conv_bytes / (conv_ms * 1e-3) / 1e9 if conv_ms > 0 else None
-    roof_conv = {"kernel": "conv_bf16 (all 11 conv launches of a step)", "bound": "mfma", "achieved": conv_tf,
+    roof_conv = {"kernel": "conv_bf16 (every conv launch of a step)", "bound": "mfma", "achieved": conv_tf,
                  "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                  "frac": conv_tf / PEAK_BF16_TFLOPS if conv_tf else None, "ms_per_step": conv_ms,
                  "algorithmic_per_step": f"{flops_tile * nt / 1e9:.1f} GFLOP ({flops_tile / 1e9:.4f} GFLOP/tile)",
@@ -361,9 +384,10 @@ def main():
         "fp32_plain": {"tiles_per_s": nt / (ms32 * 1e-3), "ms_per_step": ms32},
         "bf16_vs_fp32": ms32 / ms16,
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in sorted(kernels.items())},
+        "binning": binning_rate(work.region, ps.x, ps.y, {k: v["ms_per_step"] for k, v in kernels.items()}),
         "autotune_bf16_forward": {"choice": tune["choice"], "refine_ms_default": tune["ms_default"],
                                   "refine_ms_tuned": tune["ms_tuned"],
-                                  "configs": "0 direct (4 pixel tiles/wave), 1 LDS 16x16 tile, 2 direct (2 pixel tiles/wave), 3 LDS tile, persistent with patch prefetch"},
+                                  "configs": "0 direct (4 pixel tiles/wave), 1 LDS 16x16 tile, 2 direct (2 pixel tiles/wave), 3 LDS tile, persistent with patch prefetch, 4 (enc1b, head) fused with the layer before"},
         "tile_status_nonzero": int((status != 0).sum()),
     }
     try:
@@ -640,6 +664,7 @@ def bench_stream(dev, splat_points: int = 500_000_000, splat_tiles: int = 256):
     stages = kernel_ms(lambda: whole(ls.ORDER_LONGEST_FIRST), ["bin_count", "bin_scan", "bin_scatter", "recon_tile",
                                                                "conv_bf16"], reps=3, warm=1)
     out["stage_ms"] = stages
+    out["binning"] = binning_rate(region, x, y, stages)
     if stages.get("recon_tile"):
         out["recon_hbm_frac"] = nt * R * R * 8 * 4 / (stages["recon_tile"] * 1e-3) / 1e9 / PEAK_HBM_GBS
     if stages.get("conv_bf16"):
