@@ -376,7 +376,9 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
     SrcPart g = bsrc(W.gy8, 8, res);
     g.oy = pad;
     g.ox = pad;
-    const int rc = ls_bf16_dgrad_split(one(g), B, R, HEAD, W.wdb, W.dXC, nullptr, 0, A(iA10), g0, 16, st);
+    // the last 8 channels only feed grad_x: without it, only dA10 is computed
+    const int rc =
+        ls_bf16_dgrad_split(one(g), B, R, HEAD, W.wdb, grad_x ? W.dXC : nullptr, nullptr, 0, A(iA10), g0, 16, st);
     if (rc == LS_ENOTIMPL) {
       LS_TRY(ls_bf16_dgrad(one(g), B, R, HEAD, W.wdb, W.dXC, nullptr, nullptr, st));
       // decoder level 1: dA10 is the first 16 of the head input's 24 channels

@@ -808,7 +808,22 @@ __global__ void k_mask_round_ex(const float* __restrict__ src, int stride, int c
 }
 
 // [npix][4] FP32 -> [npix][8] BF16 with channels 4..7 zero
+// one pixel per thread: its 4 FP32 channels in, 8 BF16 channels (the last 4
+// zero) out as one 16-byte store
 __global__ void k_embed8_bf16(const float* __restrict__ g, uint16_t* __restrict__ out, int64_t npix) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= npix) return;
+  const float4 v = *reinterpret_cast<const float4*>(g + 4 * i);
+  uint4 o;
+  o.x = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+  o.y = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+  o.z = 0u;
+  o.w = 0u;
+  *reinterpret_cast<uint4*>(out + 8 * i) = o;
+}
+
+// the same, one output element per thread (any alignment)
+__global__ void k_embed8_bf16_s(const float* __restrict__ g, uint16_t* __restrict__ out, int64_t npix) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= npix * 8) return;
   const int c = (int)(i & 7);
@@ -852,7 +867,10 @@ int ls_bf16_mask_round_ex(const float* src, int stride, int coff, const uint16_t
 
 int ls_bf16_embed8(const float* g, uint16_t* out, int64_t npix, hipStream_t st) {
   LS_TRACE("embed8", st);
-  hipLaunchKernelGGL(k_embed8_bf16, dim3((unsigned)((npix * 8 + 255) / 256)), dim3(256), 0, st, g, out, npix);
+  if (reinterpret_cast<uintptr_t>(g) % 16 || reinterpret_cast<uintptr_t>(out) % 16)
+    hipLaunchKernelGGL(k_embed8_bf16_s, dim3((unsigned)((npix * 8 + 255) / 256)), dim3(256), 0, st, g, out, npix);
+  else
+    hipLaunchKernelGGL(k_embed8_bf16, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, g, out, npix);
   LS_LAUNCH_CHECK();
   return LS_OK;
 }
@@ -959,7 +977,8 @@ int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int l, const uint16_t* d
     a.up_out = up_out;
     a.up_c = up_c;
   } else {
-    // channels below split: masked BF16, split per pixel
+    // channels below split: masked BF16, split per pixel; the others FP32,
+    // or not computed at all when out is null
     a.out_bf16 = out_masked;
     a.out_f32 = nullptr;
     a.out_stride = split;
@@ -967,8 +986,9 @@ int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int l, const uint16_t* d
     a.mask = mask;
     a.split = split;
     a.out2_f32 = out;
+    if (!out) a.cout = split;
   }
-  return ls_bf16_conv_pipe(a, (cin + 15) / 16, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr,
+  return ls_bf16_conv_pipe(a, (a.cout + 15) / 16, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr,
                            s.b.c > 0 && s.b.f32 != nullptr, st, "dgrad_bf16");
 }
 
@@ -1670,6 +1690,7 @@ int ls_bf16_conv_pipe(const ConvTileArgs& a, int nt, int ca, int cb, bool upa, b
   LS_PIPE_G(1, 32, 0, false, false, false, 2)
   // the input gradients of the U-Net (gradient channels -> layer input channels)
   LS_PIPE_G(2, 8, 0, false, false, false, 2)
+  LS_PIPE_G(1, 8, 0, false, false, false, 2)
   LS_PIPE_G(1, 16, 0, false, false, false, 2)
   LS_PIPE_G(3, 16, 0, false, false, false, 2)
   LS_PIPE_G(6, 32, 0, false, false, false, 1)

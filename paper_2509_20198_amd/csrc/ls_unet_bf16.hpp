@@ -31,7 +31,7 @@ int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpa
 // upsampling adjoint into up_out (FP32, half resolution), the others FP32
 // into out (cin - up_c channels); else channels [0, split) masked by `mask`
 // into out_masked (BF16, split channels), the others FP32 into out
-// (cin - split channels).
+// (cin - split channels; not computed when out is null).
 int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, float* out,
                         float* up_out, int up_c, const uint16_t* mask, uint16_t* out_masked, int split, hipStream_t st);
 int ls_bf16_mask_round_ex(const float* src, int stride, int coff, const uint16_t* act, const float* low, int B, int H,
