@@ -372,15 +372,46 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   }
   const SrcPart XB = bsrc(W.xb, 8, R);
   int xc_stride = 8, xc_off = 0;
-  {
-    SrcPart g = bsrc(W.gy8, 8, res);
-    g.oy = pad;
-    g.ox = pad;
+  SrcPart u8 = P(iA8, 32, R2);
+  u8.up = 1;
+  SrcPart gy = bsrc(W.gy8, 8, res);
+  gy.oy = pad;
+  gy.ox = pad;
+  // Without grad_x the gradients of decoder level 1 are computed only where
+  // they can be nonzero: the head's output gradient lives on the crop, so
+  // dA10 on the crop grown by one texel and dA9 by two (clipped to the
+  // plane), stored as window tensors; their weight gradients sum over those
+  // windows only.  dU1 (read by the encoder) stays a whole plane.
+  const int h0 = std::max(0, pad - 1), h1 = std::min(R, pad + res + 1), hn = h1 - h0;
+  const int d0 = std::max(0, h0 - 1), d1 = std::min(R, h1 + 1), dn = d1 - d0;
+  SrcPart g1src = bsrc(g1, 16, R);
+  bool windowed = false;
+  if (!grad_x) {
+    const int rc = ls_bf16_dgrad_win(one(gy), B, R, HEAD, W.wdb, h0, h0, hn, A(iA10), g0, 16, st);
+    if (rc != LS_ENOTIMPL) {
+      LS_TRY(rc);
+      SrcPart g0w = bsrc(g0, 16, hn);
+      g0w.oy = h0;
+      g0w.ox = h0;
+      const int rc2 = ls_bf16_dgrad_win(one(g0w), B, R, D1B, W.wdb, d0, d0, dn, A(iA9), g1, 16, st);
+      if (rc2 != LS_ENOTIMPL) {
+        LS_TRY(rc2);
+        LS_TRY(wgrad_bf16(two(P(iA10, 16, R), XB), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
+        LS_TRY(wgrad_bf16(one(P(iA9, 16, R)), B, R, D1B, g0, 16, h0, h0, hn, hn, grad_w, W.partial, st));
+        LS_TRY(wgrad_bf16(two(u8, P(iA2, 16, R)), B, R, D1A, g1, 16, d0, d0, dn, dn, grad_w, W.partial, st));
+        g1src = bsrc(g1, 16, dn);
+        g1src.oy = d0;
+        g1src.ox = d0;
+        windowed = true;
+      }
+    }
+  }
+  if (!windowed) {
     // the last 8 channels only feed grad_x: without it, only dA10 is computed
     const int rc =
-        ls_bf16_dgrad_split(one(g), B, R, HEAD, W.wdb, grad_x ? W.dXC : nullptr, nullptr, 0, A(iA10), g0, 16, st);
+        ls_bf16_dgrad_split(one(gy), B, R, HEAD, W.wdb, grad_x ? W.dXC : nullptr, nullptr, 0, A(iA10), g0, 16, st);
     if (rc == LS_ENOTIMPL) {
-      LS_TRY(ls_bf16_dgrad(one(g), B, R, HEAD, W.wdb, W.dXC, nullptr, nullptr, st));
+      LS_TRY(ls_bf16_dgrad(one(gy), B, R, HEAD, W.wdb, W.dXC, nullptr, nullptr, st));
       // decoder level 1: dA10 is the first 16 of the head input's 24 channels
       LS_TRY(ls_bf16_mask_round_ex(W.dXC, 24, 0, A(iA10), nullptr, B, R, 16, g0, st));
       xc_stride = 24;
@@ -388,22 +419,19 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
     } else {
       LS_TRY(rc);
     }
+    LS_TRY(wgrad_bf16(two(P(iA10, 16, R), XB), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
+    LS_TRY(wg(D1B, g0, one(P(iA9, 16, R)), R));
+    LS_TRY(dg(D1B, g0, R, nullptr, iA9, g1));
+    LS_TRY(wg(D1A, g1, two(u8, P(iA2, 16, R)), R));
   }
-  LS_TRY(wgrad_bf16(two(P(iA10, 16, R), XB), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
-  LS_TRY(wg(D1B, g0, one(P(iA9, 16, R)), R));
-  LS_TRY(dg(D1B, g0, R, nullptr, iA9, g1));
-  SrcPart u8 = P(iA8, 32, R2);
-  u8.up = 1;
-  LS_TRY(wg(D1A, g1, two(u8, P(iA2, 16, R)), R));
   // dU1: the upsampled part's 32 channels go straight to their upsampling
   // adjoint dA8 when the persistent form runs, the skip part's 16 stay in
   // dU1 (u1_stride channels from u1_off)
   int u1_stride = 16, u1_off = 0;
   {
-    const int rc = ls_bf16_dgrad_split(one(bsrc(g1, 16, R)), B, R, D1A, W.wdb, W.dU1, W.dA8, 32, nullptr, nullptr, 0,
-                                       st);
+    const int rc = ls_bf16_dgrad_split(one(g1src), B, R, D1A, W.wdb, W.dU1, W.dA8, 32, nullptr, nullptr, 0, st);
     if (rc == LS_ENOTIMPL) {
-      LS_TRY(dg(D1A, g1, R, W.dU1, -1, nullptr));
+      LS_TRY(ls_bf16_dgrad(one(g1src), B, R, D1A, W.wdb, W.dU1, nullptr, nullptr, st));
       LS_TRY(ls_up_adjoint(W.dU1, 48, W.dA8, B, R2, R2, 32, st));
       u1_stride = 48;
       u1_off = 32;

@@ -426,10 +426,13 @@ __device__ __forceinline__ void conv_tile_store_t(const ConvTileArgs& A, const f
     }
     if (A.mask) {
       // the backward's ReLU' of the layer below, 4 channels of each pixel
+      const int64_t moff = A.mask_w ? (((int64_t)b * A.mask_h + oy0 + A.mask_y0) * A.mask_w + ox + A.mask_x0) * ostr + c0
+                                    : off0;
+      const int64_t mrow = A.mask_w ? (int64_t)A.mask_w * ostr : row;
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt)
         if (full || (oy0 + mt < A.Ho && ox < A.Wo)) {
-          const uint2 mv = *reinterpret_cast<const uint2*>(A.mask + off0 + mt * row);
+          const uint2 mv = *reinterpret_cast<const uint2*>(A.mask + moff + mt * mrow);
           const uint32_t mw[2] = {mv.x, mv.y};
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -989,6 +992,45 @@ int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int l, const uint16_t* d
     if (!out) a.cout = split;
   }
   return ls_bf16_conv_pipe(a, (a.cout + 15) / 16, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr,
+                           s.b.c > 0 && s.b.f32 != nullptr, st, "dgrad_bf16");
+}
+
+int ls_bf16_dgrad_win(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked, int y0, int x0, int n,
+                      const uint16_t* mask_plane, uint16_t* out_masked, int split, hipStream_t st) {
+  const int cin = LS_LAYERS[l].cin;
+  if (s.a.c + s.b.c != dgrad_cg(l)) return LS_EINVAL;
+  if (y0 < 0 || x0 < 0 || n <= 0 || y0 + n > H || x0 + n > H || !mask_plane || !out_masked) return LS_EINVAL;
+  const int cfg = ls_conv_config_get(l, LS_BF16, 1);
+  if (!(cfg < 0 || cfg == 2) || split <= 0 || split % 16 || split > cin) return LS_ENOTIMPL;
+  ConvTileArgs a;
+  a.src = s;
+  a.B = B;
+  a.H = H;
+  a.W = H;
+  a.y0 = y0;
+  a.x0 = x0;
+  a.Ho = n;
+  a.Wo = n;
+  a.tiles_x = (n + TT - 1) / TT;
+  a.tiles_y = (n + TT - 1) / TT;
+  a.wp = dpacked + ls_bf16_dpacked_offset(l);
+  a.Kpad = dgrad_kpad(l);
+  a.bias = nullptr;
+  a.cout = split;
+  a.relu = 0;
+  a.out_bf16 = out_masked;
+  a.out_f32 = nullptr;
+  a.out_stride = split;
+  a.out_coff = 0;
+  a.pool_out = nullptr;
+  a.pool_stride = 0;
+  a.pool_coff = 0;
+  a.mask = mask_plane;
+  a.mask_h = H;
+  a.mask_w = H;
+  a.mask_y0 = y0;
+  a.mask_x0 = x0;
+  return ls_bf16_conv_pipe(a, split / 16, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr,
                            s.b.c > 0 && s.b.f32 != nullptr, st, "dgrad_bf16");
 }
 

@@ -34,6 +34,13 @@ int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpa
 // (cin - split channels; not computed when out is null).
 int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, float* out,
                         float* up_out, int up_c, const uint16_t* mask, uint16_t* out_masked, int split, hipStream_t st);
+// The input gradient on the output window [y0, y0 + n) x [x0, x0 + n) of
+// the H x H plane, its first `split` channels masked by the activation
+// `mask_plane` (a whole [B][H][H][split] plane) into out_masked (BF16,
+// [B][n][n][split]); the other channels are not computed.  Persistent tile
+// form only (LS_ENOTIMPL otherwise).
+int ls_bf16_dgrad_win(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, int y0, int x0, int n,
+                      const uint16_t* mask_plane, uint16_t* out_masked, int split, hipStream_t st);
 int ls_bf16_mask_round_ex(const float* src, int stride, int coff, const uint16_t* act, const float* low, int B, int H,
                           int C, uint16_t* out, hipStream_t st);
 
@@ -62,6 +69,10 @@ struct ConvTileArgs {
   int up_c = 0;
   int split = 0;
   float* out2_f32 = nullptr;
+  // a windowed output's mask read from a larger plane [B][mask_h][mask_w]
+  // [out_stride], the window's pixel (0, 0) at (mask_y0, mask_x0); mask_w 0:
+  // the mask has the output's layout (persistent form only)
+  int mask_h = 0, mask_w = 0, mask_y0 = 0, mask_x0 = 0;
 };
 
 // Persistent pipelined BF16 conv (weights in LDS, next patch prefetched) on

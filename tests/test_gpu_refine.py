@@ -347,6 +347,51 @@ def test_bf16_random_weights_within_accumulation_spread():
     assert ey <= 3 * ey_alt + 1e-5 and ex <= 3 * ex_alt + 1e-3
 
 
+def test_bf16_backward_without_grad_x_all_active():
+    """Without grad_x the level-1 decoder gradients are computed on windows
+    around the crop only; the weight gradient still meets the BF16-form
+    reference per layer."""
+    from oracle import unet_bf16
+
+    wts, x32, G, _, _, _ = _bf16_case(True)
+    g = ls.Grid.of(synth.Region(tiles_x=2, tiles_y=2))
+    wt = torch.from_numpy(wts.astype(np.float32)).cuda()
+    gw, gx = ls.refine_backward(wt, torch.from_numpy(x32.astype(np.float32)).cuda(),
+                                torch.from_numpy(G.astype(np.float32)).cuda(), g, ls.BF16,
+                                w_bf16=ls.pack_weights_bf16(wt), want_grad_x=False)
+    torch.cuda.synchronize()
+    assert gx is None
+    gw_ref, _ = unet_bf16.backward(wts, x32, G, 64, 16)
+    layers = _layer_rel(gw.cpu().numpy().astype(np.float64), gw_ref)
+    print("all-active bf16 without grad_x: " + " ".join(f"{n} {r:.1e}" for n, r in layers))
+    for n, r in layers:
+        assert r <= 1e-3, (n, r)
+
+
+@pytest.mark.parametrize("pad", [16, 4, 0])
+def test_bf16_backward_windows_equal_whole_planes(pad):
+    """The windowed level-1 gradients (no grad_x) against the whole-plane
+    path (grad_x requested): the same masked BF16 gradients, summed over
+    other pixel chunks, so per layer equal up to FP32 summation order."""
+    res = 64
+    region = synth.Region(tiles_x=2, tiles_y=2, res=res, pad=pad)
+    g = ls.Grid.of(region)
+    R = g.R
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.randn((3, R, R, 8), device="cuda", generator=gen) * 0.3
+    wts = synth.unet_weights(1, head_std=0.05, bias_std=0.05)
+    wt = torch.from_numpy(wts.astype(np.float32)).cuda()
+    wb = ls.pack_weights_bf16(wt)
+    gy = torch.randn((3, res, res, 4), device="cuda", generator=gen)
+    gw_w, _ = ls.refine_backward(wt, x, gy, g, ls.BF16, w_bf16=wb, want_grad_x=False)
+    gw_f, _ = ls.refine_backward(wt, x, gy, g, ls.BF16, w_bf16=wb, want_grad_x=True)
+    torch.cuda.synchronize()
+    layers = _layer_rel(gw_w.cpu().numpy().astype(np.float64), gw_f.cpu().numpy().astype(np.float64))
+    print(f"pad {pad}: windowed vs whole planes " + " ".join(f"{n} {r:.1e}" for n, r in layers))
+    for n, r in layers:
+        assert r <= 1e-5, (n, r)
+
+
 def test_backward_bf16_saved_activations_equal_recompute():
     w, xo, wts, G, g, xt, wt, gt, wb, gw, gx = _backward_case(ls.BF16, want_gx=False)
     act = torch.empty(ls.act_bytes(g, xt.shape[0], ls.BF16), dtype=torch.uint8, device="cuda")
