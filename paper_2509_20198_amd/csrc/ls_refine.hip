@@ -428,8 +428,21 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   // adjoint dA8 when the persistent form runs, the skip part's 16 stay in
   // dU1 (u1_stride channels from u1_off)
   int u1_stride = 16, u1_off = 0;
+  // with the windows, dU1 and its upsampling adjoint dA8 too are computed
+  // only where dA9 reaches (window origin and size even for the 2 x 2 sums)
+  int u0 = 0, un = 0;
+  if (windowed) {
+    u0 = std::max(0, d0 - 1) & ~1;
+    un = std::min(R, (d1 + 2) & ~1) - u0;
+  }
   {
-    const int rc = ls_bf16_dgrad_split(one(g1src), B, R, D1A, W.wdb, W.dU1, W.dA8, 32, nullptr, nullptr, 0, st);
+    int rc = LS_ENOTIMPL;
+    if (windowed) {
+      rc = ls_bf16_dgrad_split(one(g1src), B, R, D1A, W.wdb, W.dU1, W.dA8, 32, nullptr, nullptr, 0, st, u0, un);
+      if (rc == LS_ENOTIMPL) un = 0;
+    }
+    if (!windowed || rc == LS_ENOTIMPL)
+      rc = ls_bf16_dgrad_split(one(g1src), B, R, D1A, W.wdb, W.dU1, W.dA8, 32, nullptr, nullptr, 0, st);
     if (rc == LS_ENOTIMPL) {
       LS_TRY(ls_bf16_dgrad(one(g1src), B, R, D1A, W.wdb, W.dU1, nullptr, nullptr, st));
       LS_TRY(ls_up_adjoint(W.dU1, 48, W.dA8, B, R2, R2, 32, st));
@@ -440,7 +453,7 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
     }
   }
   // decoder level 2
-  LS_TRY(ls_bf16_mask_round_ex(W.dA8, 32, 0, A(iA8), nullptr, B, R2, 32, g0, st));
+  LS_TRY(ls_bf16_mask_round_ex(W.dA8, 32, 0, A(iA8), nullptr, B, R2, 32, g0, st, u0 / 2, un / 2));
   LS_TRY(wg(D2B, g0, one(P(iA7, 32, R2)), R2));
   LS_TRY(dg(D2B, g0, R2, nullptr, iA7, g1));
   SrcPart u6 = P(iA6, 64, R4);
@@ -472,7 +485,7 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   LS_TRY(wg(E2A, g1, one(P(iP1, 16, R2)), R2));
   LS_TRY(dg(E2A, g1, R2, W.dP1, -1, nullptr));
   // encoder level 1: dA2 = skip slice of dU1 + pool adjoint of dP1
-  LS_TRY(ls_bf16_mask_round_ex(W.dU1, u1_stride, u1_off, A(iA2), W.dP1, B, R, 16, g0, st));
+  LS_TRY(ls_bf16_mask_round_ex(W.dU1, u1_stride, u1_off, A(iA2), W.dP1, B, R, 16, g0, st, u0, un));
   LS_TRY(wg(E1B, g0, one(P(iA1, 16, R)), R));
   LS_TRY(dg(E1B, g0, R, nullptr, iA1, g1));
   LS_TRY(wg(E1A, g1, one(XB), R));

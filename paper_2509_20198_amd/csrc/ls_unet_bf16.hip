@@ -782,21 +782,35 @@ __global__ void k_mask_round_bf16(const float* __restrict__ g, const uint16_t* _
 // of a half-resolution gradient: the channel split, the pool adjoint and the
 // masking of the backward in one pass.
 __global__ void k_mask_round_ex(const float* __restrict__ src, int stride, int coff, const uint16_t* __restrict__ act,
-                                const float* __restrict__ low, int B, int H, int W, int C, uint16_t* __restrict__ out) {
+                                const float* __restrict__ low, int B, int H, int W, int C, int sy0, int sn,
+                                uint16_t* __restrict__ out) {
   const int c8n = C / 8;
   const int64_t n = (int64_t)B * H * W * c8n;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int c0 = 8 * (int)(i % c8n);
   const int64_t p = i / c8n;
-  const float* sp = src + p * stride + coff + c0;
-  const float4 a0 = *reinterpret_cast<const float4*>(sp), a1 = *reinterpret_cast<const float4*>(sp + 4);
-  float g[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+  const int x = (int)(p % W);
+  const int64_t r = p / W;
+  const int y = (int)(r % H);
+  const int b = (int)(r / H);
+  float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // src: the whole plane (sn = 0) or the window [sy0, sy0 + sn)^2, zero outside
+  const int wy = y - sy0, wx = x - sy0;
+  if (sn == 0 || (wy >= 0 && wx >= 0 && wy < sn && wx < sn)) {
+    const int64_t si = sn == 0 ? p : ((int64_t)b * sn + wy) * sn + wx;
+    const float* sp = src + si * stride + coff + c0;
+    const float4 a0 = *reinterpret_cast<const float4*>(sp), a1 = *reinterpret_cast<const float4*>(sp + 4);
+    g[0] = a0.x;
+    g[1] = a0.y;
+    g[2] = a0.z;
+    g[3] = a0.w;
+    g[4] = a1.x;
+    g[5] = a1.y;
+    g[6] = a1.z;
+    g[7] = a1.w;
+  }
   if (low) {
-    const int x = (int)(p % W);
-    const int64_t r = p / W;
-    const int y = (int)(r % H);
-    const int b = (int)(r / H);
     const float* lp = low + (((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c0;
     const float4 l0 = *reinterpret_cast<const float4*>(lp), l1 = *reinterpret_cast<const float4*>(lp + 4);
     const float lv[8] = {l0.x, l0.y, l0.z, l0.w, l1.x, l1.y, l1.z, l1.w};
@@ -858,12 +872,13 @@ int ls_bf16_mask_round(const float* g, const uint16_t* act, uint16_t* out, int64
 }
 
 int ls_bf16_mask_round_ex(const float* src, int stride, int coff, const uint16_t* act, const float* low, int B,
-                          int H, int C, uint16_t* out, hipStream_t st) {
+                          int H, int C, uint16_t* out, hipStream_t st, int sy0, int sn) {
   if (C % 8 || stride % 4 || coff % 4) return LS_ENOTIMPL;
   LS_TRACE("mask_round", st);
   const int64_t n = (int64_t)B * H * H * (C / 8);
+  if (sn < 0 || sy0 < 0 || sy0 + sn > H) return LS_EINVAL;
   hipLaunchKernelGGL(k_mask_round_ex, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, stride, coff, act, low,
-                     B, H, H, C, out);
+                     B, H, H, C, sy0, sn, out);
   LS_LAUNCH_CHECK();
   return LS_OK;
 }
@@ -943,25 +958,33 @@ int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked
 }
 
 int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked, float* out, float* up_out,
-                        int up_c, const uint16_t* mask, uint16_t* out_masked, int split, hipStream_t st) {
+                        int up_c, const uint16_t* mask, uint16_t* out_masked, int split, hipStream_t st, int y0,
+                        int n) {
   const int cin = LS_LAYERS[l].cin;
   if (s.a.c + s.b.c != dgrad_cg(l)) return LS_EINVAL;
+  if (n == 0) {
+    y0 = 0;
+    n = H;
+  }
+  if (y0 < 0 || n < 0 || y0 + n > H) return LS_EINVAL;
   const int cfg = ls_conv_config_get(l, LS_BF16, 1);
   if (!(cfg < 0 || cfg == 2)) return LS_ENOTIMPL;
-  // whole 16-channel tiles on each side of the split; even planes for the 2 x 2 sums
-  if (up_c > 0 ? (up_c % 16 || up_c >= cin || H % 2) : (split <= 0 || split % 16 || split >= cin || !mask))
+  // whole 16-channel tiles on each side of the split; even windows for the
+  // 2 x 2 sums; the masked split only on the whole plane
+  if (up_c > 0 ? (up_c % 16 || up_c >= cin || y0 % 2 || n % 2)
+               : (split <= 0 || split % 16 || split >= cin || !mask || n != H))
     return LS_ENOTIMPL;
   ConvTileArgs a;
   a.src = s;
   a.B = B;
   a.H = H;
   a.W = H;
-  a.y0 = 0;
-  a.x0 = 0;
-  a.Ho = H;
-  a.Wo = H;
-  a.tiles_x = (H + TT - 1) / TT;
-  a.tiles_y = (H + TT - 1) / TT;
+  a.y0 = y0;
+  a.x0 = y0;
+  a.Ho = n;
+  a.Wo = n;
+  a.tiles_x = (n + TT - 1) / TT;
+  a.tiles_y = (n + TT - 1) / TT;
   a.wp = dpacked + ls_bf16_dpacked_offset(l);
   a.Kpad = dgrad_kpad(l);
   a.bias = nullptr;

@@ -31,9 +31,12 @@ int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpa
 // upsampling adjoint into up_out (FP32, half resolution), the others FP32
 // into out (cin - up_c channels); else channels [0, split) masked by `mask`
 // into out_masked (BF16, split channels), the others FP32 into out
-// (cin - split channels; not computed when out is null).
+// (cin - split channels; not computed when out is null).  n > 0 (up_c > 0
+// only, y0 and n even): only the output window [y0, y0 + n)^2, out as
+// [B][n][n] and up_out as [B][n/2][n/2] window tensors.
 int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, float* out,
-                        float* up_out, int up_c, const uint16_t* mask, uint16_t* out_masked, int split, hipStream_t st);
+                        float* up_out, int up_c, const uint16_t* mask, uint16_t* out_masked, int split, hipStream_t st,
+                        int y0 = 0, int n = 0);
 // The input gradient on the output window [y0, y0 + n) x [x0, x0 + n) of
 // the H x H plane, its first `split` channels masked by the activation
 // `mask_plane` (a whole [B][H][H][split] plane) into out_masked (BF16,
@@ -41,8 +44,10 @@ int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int layer, const uint16_
 // form only (LS_ENOTIMPL otherwise).
 int ls_bf16_dgrad_win(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, int y0, int x0, int n,
                       const uint16_t* mask_plane, uint16_t* out_masked, int split, hipStream_t st);
+// (sn > 0: src is the window tensor [B][sn][sn][stride] of the plane's
+// pixels [sy0, sy0 + sn)^2, zero outside it)
 int ls_bf16_mask_round_ex(const float* src, int stride, int coff, const uint16_t* act, const float* low, int B, int H,
-                          int C, uint16_t* out, hipStream_t st);
+                          int C, uint16_t* out, hipStream_t st, int sy0 = 0, int sn = 0);
 
 // One 3x3 conv as 16 x 16 output tiles (LDS-staged input patch), the form
 // every persistent BF16 conv launch takes.
