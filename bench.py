@@ -557,6 +557,9 @@ def bench_training(dev, train_steps: int = 60):
     for key, kind, tex in (("train_bf16", ls.LOSS_L1, tex_max), ("train_bf16_paper_loss", ls.LOSS_CLIPPED_MSE,
                                                                  tex_mean)):
         base = T.loss_value(T.linear_baseline(x, g.pad, g.res), tex, cz, g, kind)
+        # one untimed step of a throwaway trainer first, so the timed steps
+        # find the activation and workspace buffers in torch's caching allocator
+        T.Trainer(w0, g, ls.BF16, save_acts=True, total_steps=train_steps, loss_kind=kind).step(x, tex, cz)
         tr = T.Trainer(w0, g, ls.BF16, save_acts=True, total_steps=train_steps, loss_kind=kind)
         losses = []
         torch.cuda.synchronize()
