@@ -377,36 +377,33 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   SrcPart gy = bsrc(W.gy8, 8, res);
   gy.oy = pad;
   gy.ox = pad;
-  // Without grad_x the gradients of decoder level 1 are computed only where
-  // they can be nonzero: the head's output gradient lives on the crop, so
-  // dA10 on the crop grown by one texel and dA9 by two (clipped to the
-  // plane), stored as window tensors; their weight gradients sum over those
-  // windows only.  dU1 (read by the encoder) stays a whole plane.
-  const int h0 = std::max(0, pad - 1), h1 = std::min(R, pad + res + 1), hn = h1 - h0;
-  const int d0 = std::max(0, h0 - 1), d1 = std::min(R, h1 + 1), dn = d1 - d0;
+  // The gradients of decoder level 1 are computed only where they can be
+  // nonzero: the head's output gradient lives on the crop, so dA10 on the
+  // crop grown by one texel and dA9 by two (clipped to the plane), stored as
+  // window tensors, with the ReLU masks A10 and A9 that the forward saved on
+  // the same windows; their weight gradients sum over those windows only.
+  const Lvl1Win lw = ls_lvl1_windows(R, pad, res);
+  const int h0 = lw.h0, hn = lw.hn, d0 = lw.d0, dn = lw.dn, d1 = d0 + dn;
   SrcPart g1src = bsrc(g1, 16, R);
-  bool windowed = false;
-  if (!grad_x) {
-    const int rc = ls_bf16_dgrad_win(one(gy), B, R, HEAD, W.wdb, h0, h0, hn, A(iA10), g0, 16, st);
-    if (rc != LS_ENOTIMPL) {
-      LS_TRY(rc);
-      SrcPart g0w = bsrc(g0, 16, hn);
-      g0w.oy = h0;
-      g0w.ox = h0;
-      const int rc2 = ls_bf16_dgrad_win(one(g0w), B, R, D1B, W.wdb, d0, d0, dn, A(iA9), g1, 16, st);
-      if (rc2 != LS_ENOTIMPL) {
-        LS_TRY(rc2);
-        LS_TRY(wgrad_bf16(two(P(iA10, 16, R), XB), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
-        LS_TRY(wgrad_bf16(one(P(iA9, 16, R)), B, R, D1B, g0, 16, h0, h0, hn, hn, grad_w, W.partial, st));
-        LS_TRY(wgrad_bf16(two(u8, P(iA2, 16, R)), B, R, D1A, g1, 16, d0, d0, dn, dn, grad_w, W.partial, st));
-        g1src = bsrc(g1, 16, dn);
-        g1src.oy = d0;
-        g1src.ox = d0;
-        windowed = true;
-      }
-    }
-  }
-  if (!windowed) {
+  const bool windowed = ls_bf16_lvl1_windowed();
+  if (windowed) {
+    SrcPart a9 = P(iA9, 16, dn), a10 = P(iA10, 16, hn);
+    a9.oy = a9.ox = d0;
+    a10.oy = a10.ox = h0;
+    // dA10 and, for grad_x, the input skip's 8 channels (FP32 window tensor)
+    int rc = ls_bf16_dgrad_win(one(gy), B, R, HEAD, W.wdb, h0, h0, hn, A(iA10), hn, h0, g0, 16,
+                               grad_x ? W.dXC : nullptr, st);
+    LS_TRY(rc);
+    SrcPart g0w = bsrc(g0, 16, hn);
+    g0w.oy = g0w.ox = h0;
+    rc = ls_bf16_dgrad_win(one(g0w), B, R, D1B, W.wdb, d0, d0, dn, A(iA9), dn, d0, g1, 16, nullptr, st);
+    LS_TRY(rc);
+    LS_TRY(wgrad_bf16(two(a10, XB), B, R, HEAD, W.gy8, 8, pad, pad, res, res, grad_w, W.partial, st));
+    LS_TRY(wgrad_bf16(one(a9), B, R, D1B, g0, 16, h0, h0, hn, hn, grad_w, W.partial, st));
+    LS_TRY(wgrad_bf16(two(u8, P(iA2, 16, R)), B, R, D1A, g1, 16, d0, d0, dn, dn, grad_w, W.partial, st));
+    g1src = bsrc(g1, 16, dn);
+    g1src.oy = g1src.ox = d0;
+  } else {
     // the last 8 channels only feed grad_x: without it, only dA10 is computed
     const int rc =
         ls_bf16_dgrad_split(one(gy), B, R, HEAD, W.wdb, grad_x ? W.dXC : nullptr, nullptr, 0, A(iA10), g0, 16, st);
@@ -491,7 +488,10 @@ int backward_bf16(const float* x, const uint16_t* acts, const float* grad_y, int
   LS_TRY(wg(E1A, g1, one(XB), R));
   if (grad_x) {
     LS_TRY(dg(E1A, g1, R, grad_x, -1, nullptr));
-    LS_TRY(ls_copy_channels(W.dXC, xc_stride, xc_off, grad_x, 8, B * f, 1, st));
+    if (windowed)
+      LS_TRY(ls_add_window(W.dXC, hn, h0, grad_x, R, B, 8, st));
+    else
+      LS_TRY(ls_copy_channels(W.dXC, xc_stride, xc_off, grad_x, 8, B * f, 1, st));
     LS_TRY(ls_residual_adjoint(grad_y, grad_x, B, res, pad, st));
   }
   return LS_OK;

@@ -810,6 +810,21 @@ __global__ void k_copy_channels(const float* __restrict__ src, int stride, int c
   dst[i] = accumulate ? dst[i] + v : v;
 }
 
+// dst[b][y0 + y][y0 + x][c] += src[b][y][x][c]: a window tensor of C
+// channels added into the H x H plane
+__global__ void k_add_window(const float* __restrict__ src, int n, int y0, float* __restrict__ dst, int H, int B,
+                             int C) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)B * n * n * C) return;
+  const int c = (int)(i % C);
+  int64_t r = i / C;
+  const int x = (int)(r % n);
+  r /= n;
+  const int y = (int)(r % n);
+  const int b = (int)(r / n);
+  dst[(((int64_t)b * H + y0 + y) * H + y0 + x) * C + c] += src[i];
+}
+
 // dHigh += 0.25 * spread(dLow): adjoint of 2x2 average pooling
 __global__ void k_pool_adjoint_add(const float* __restrict__ dlow, float* __restrict__ dhigh, int B, int H, int W, int C) {
   const int64_t n = (int64_t)B * H * W * C;
@@ -986,6 +1001,15 @@ int ls_up_adjoint(const float* dhigh, int stride, float* dlow, int B, int h, int
 int ls_copy_channels(const float* src, int stride, int coff, float* dst, int C, int64_t npix, int acc, hipStream_t st) {
   LS_TRACE("copy_channels", st);
   hipLaunchKernelGGL(k_copy_channels, dim3(nblk(npix * C)), dim3(CT), 0, st, src, stride, coff, dst, C, npix, acc);
+  LS_LAUNCH_CHECK();
+  return LS_OK;
+}
+
+int ls_add_window(const float* src, int n, int y0, float* dst, int H, int B, int C, hipStream_t st) {
+  if (n <= 0 || B <= 0) return LS_OK;
+  if (y0 < 0 || y0 + n > H) return LS_EINVAL;
+  LS_TRACE("copy_channels", st);
+  hipLaunchKernelGGL(k_add_window, dim3(nblk((int64_t)B * n * n * C)), dim3(CT), 0, st, src, n, y0, dst, H, B, C);
   LS_LAUNCH_CHECK();
   return LS_OK;
 }

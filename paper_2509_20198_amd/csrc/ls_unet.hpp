@@ -71,5 +71,7 @@ int ls_prep_weights(const float* w, float* wt, float* wd, hipStream_t st);
 int ls_wgrad_f32(const WgradArgs& a, float* grad_w_layer, hipStream_t st);
 int ls_up_adjoint(const float* dhigh, int stride, float* dlow, int B, int h, int w, int c_low, hipStream_t st);
 int ls_copy_channels(const float* src, int stride, int coff, float* dst, int C, int64_t npix, int acc, hipStream_t st);
+// dst [B][H][H][C] += src, the window tensor [B][n][n][C] of the pixels [y0, y0 + n)^2
+int ls_add_window(const float* src, int n, int y0, float* dst, int H, int B, int C, hipStream_t st);
 int ls_pool_adjoint_add(const float* dlow, float* dhigh, int B, int H, int W, int C, hipStream_t st);
 int ls_residual_adjoint(const float* dy, float* dx, int B, int res, int pad, hipStream_t st);

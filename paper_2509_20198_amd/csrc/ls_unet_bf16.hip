@@ -1019,12 +1019,14 @@ int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int l, const uint16_t* d
 }
 
 int ls_bf16_dgrad_win(const ConvSrc& s, int B, int H, int l, const uint16_t* dpacked, int y0, int x0, int n,
-                      const uint16_t* mask_plane, uint16_t* out_masked, int split, hipStream_t st) {
+                      const uint16_t* mask, int mask_n, int mask_o, uint16_t* out_masked, int split, float* out2,
+                      hipStream_t st) {
   const int cin = LS_LAYERS[l].cin;
   if (s.a.c + s.b.c != dgrad_cg(l)) return LS_EINVAL;
-  if (y0 < 0 || x0 < 0 || n <= 0 || y0 + n > H || x0 + n > H || !mask_plane || !out_masked) return LS_EINVAL;
+  if (y0 < 0 || x0 < 0 || n <= 0 || y0 + n > H || x0 + n > H || !mask || !out_masked) return LS_EINVAL;
+  if (y0 < mask_o || x0 < mask_o || y0 + n > mask_o + mask_n || x0 + n > mask_o + mask_n) return LS_EINVAL;
   const int cfg = ls_conv_config_get(l, LS_BF16, 1);
-  if (!(cfg < 0 || cfg == 2) || split <= 0 || split % 16 || split > cin) return LS_ENOTIMPL;
+  if (!(cfg < 0 || cfg == 2) || split <= 0 || split % 16 || split > cin || (out2 && split == cin)) return LS_ENOTIMPL;
   ConvTileArgs a;
   a.src = s;
   a.B = B;
@@ -1039,7 +1041,7 @@ int ls_bf16_dgrad_win(const ConvSrc& s, int B, int H, int l, const uint16_t* dpa
   a.wp = dpacked + ls_bf16_dpacked_offset(l);
   a.Kpad = dgrad_kpad(l);
   a.bias = nullptr;
-  a.cout = split;
+  a.cout = out2 ? cin : split;
   a.relu = 0;
   a.out_bf16 = out_masked;
   a.out_f32 = nullptr;
@@ -1048,13 +1050,25 @@ int ls_bf16_dgrad_win(const ConvSrc& s, int B, int H, int l, const uint16_t* dpa
   a.pool_out = nullptr;
   a.pool_stride = 0;
   a.pool_coff = 0;
-  a.mask = mask_plane;
-  a.mask_h = H;
-  a.mask_w = H;
-  a.mask_y0 = y0;
-  a.mask_x0 = x0;
-  return ls_bf16_conv_pipe(a, split / 16, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr,
+  a.mask = mask;
+  a.mask_h = mask_n;
+  a.mask_w = mask_n;
+  a.mask_y0 = y0 - mask_o;
+  a.mask_x0 = x0 - mask_o;
+  if (out2) {
+    a.split = split;
+    a.out2_f32 = out2;
+  }
+  return ls_bf16_conv_pipe(a, (a.cout + 15) / 16, s.a.c, s.b.c, s.a.up != 0, s.a.f32 != nullptr,
                            s.b.c > 0 && s.b.f32 != nullptr, st, "dgrad_bf16");
+}
+
+bool ls_bf16_lvl1_windowed() {
+  auto pipe = [](int l) {
+    const int c = ls_conv_config_get(l, LS_BF16, 1);
+    return c < 0 || c == 2;
+  };
+  return pipe(LS_NLAYER - 1) && pipe(LS_NLAYER - 2);
 }
 
 int ls_bf16_kpad(int l) { return (9 * LS_LAYERS[l].cin + 31) / 32 * 32; }
@@ -1710,12 +1724,34 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
                               st);
     if (rc != LS_ENOTIMPL) return rc;
   }
-  LS_TRYB(conv(cs(u8, bpart(A2, 16, R)), R, 8, A9, nullptr));
-  LS_TRYB(conv(cs(bpart(A9, 16, R), none), R, 9, A10, nullptr));
+  // the window conv of layer l from s into `out`, output [y0, y0 + n)^2
+  auto conv_win = [&](const ConvSrc& s, int l, uint16_t* out, int y0, int n) -> int {
+    if ((variant(l) == 1 || variant(l) == 3) && (size_t)PT * PT * patch_pitch(LS_LAYERS[l].cin) * 2 <= LDS_MAX)
+      return conv_bf16_lds(s, B, R, l, packed, w, out, nullptr, nullptr, 1, y0, y0, n, n, variant(l) == 3, st);
+    return conv_bf16(s, B, R, l, packed, w, out, nullptr, 1, y0, y0, n, n, variant(l) == 2 ? 2 : 4, st);
+  };
+  SrcPart a10 = bpart(A10, 16, R);
+  if (!fuse && ls_bf16_lvl1_windowed()) {
+    // saved for the backward, which then runs decoder level 1 on the same
+    // windows: A9 and A10 only where the head's output and its gradient
+    // reach, stored as window tensors
+    const Lvl1Win lw = ls_lvl1_windows(R, gi.pad, gi.res);
+    LS_TRYB(conv_win(cs(u8, bpart(A2, 16, R)), 8, A9, lw.d0, lw.dn));
+    SrcPart a9 = bpart(A9, 16, lw.dn);
+    a9.oy = lw.d0;
+    a9.ox = lw.d0;
+    LS_TRYB(conv_win(cs(a9, none), 9, A10, lw.h0, lw.hn));
+    a10 = bpart(A10, 16, lw.hn);
+    a10.oy = lw.h0;
+    a10.ox = lw.h0;
+  } else {
+    LS_TRYB(conv(cs(u8, bpart(A2, 16, R)), R, 8, A9, nullptr));
+    LS_TRYB(conv(cs(bpart(A9, 16, R), none), R, 9, A10, nullptr));
+  }
   if ((variant(10) == 1 || variant(10) == 3) && (size_t)PT * PT * patch_pitch(24) * 2 <= LDS_MAX)
-    return conv_bf16_lds(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad,
-                         gi.res, gi.res, variant(10) == 3, st);
-  return conv_bf16(cs(bpart(A10, 16, R), X), B, R, 10, packed, w, nullptr, head, 0, gi.pad, gi.pad, gi.res, gi.res,
+    return conv_bf16_lds(cs(a10, X), B, R, 10, packed, w, nullptr, head, nullptr, 0, gi.pad, gi.pad, gi.res, gi.res,
+                         variant(10) == 3, st);
+  return conv_bf16(cs(a10, X), B, R, 10, packed, w, nullptr, head, 0, gi.pad, gi.pad, gi.res, gi.res,
                    variant(10) == 2 ? 2 : 4, st);
 }
 

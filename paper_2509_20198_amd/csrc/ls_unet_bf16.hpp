@@ -37,15 +37,36 @@ int ls_bf16_dgrad(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpa
 int ls_bf16_dgrad_split(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, float* out,
                         float* up_out, int up_c, const uint16_t* mask, uint16_t* out_masked, int split, hipStream_t st,
                         int y0 = 0, int n = 0);
+// Windows of the full-resolution decoder level around the crop, where the
+// head's output and its gradient reach (all clipped to the plane): the head
+// input dA10 / A10 on the crop grown by one texel [h0, h0 + hn), dec1b's
+// input dA9 / A9 by two [d0, d0 + dn).
+struct Lvl1Win {
+  int h0, hn, d0, dn;
+};
+inline Lvl1Win ls_lvl1_windows(int R, int pad, int res) {
+  Lvl1Win w;
+  w.h0 = pad - 1 > 0 ? pad - 1 : 0;
+  const int h1 = pad + res + 1 < R ? pad + res + 1 : R;
+  w.hn = h1 - w.h0;
+  w.d0 = w.h0 - 1 > 0 ? w.h0 - 1 : 0;
+  w.dn = (h1 + 1 < R ? h1 + 1 : R) - w.d0;
+  return w;
+}
+// true when the BF16 forward that saves activations stores A9 and A10 as
+// window tensors and the backward runs decoder level 1 on the windows: the
+// input gradients of the head and dec1b use the persistent tile form
+bool ls_bf16_lvl1_windowed();
 // The input gradient on the output window [y0, y0 + n) x [x0, x0 + n) of
-// the H x H plane, its first `split` channels masked by the activation
-// `mask_plane` (a whole [B][H][H][split] plane) into out_masked (BF16,
-// [B][n][n][split]); the other channels are not computed.  Persistent tile
+// the H x H plane: its first `split` channels masked by the activation
+// `mask` into out_masked (BF16, [B][n][n][split]), the others FP32 into out2
+// ([B][n][n][cin - split]) or not computed when out2 is null.  The mask is
+// the window tensor [B][mask_n][mask_n][split] of the pixels [mask_o,
+// mask_o + mask_n)^2, which must hold the output window.  Persistent tile
 // form only (LS_ENOTIMPL otherwise).
 int ls_bf16_dgrad_win(const ConvSrc& s, int B, int H, int layer, const uint16_t* dpacked, int y0, int x0, int n,
-                      const uint16_t* mask_plane, uint16_t* out_masked, int split, hipStream_t st);
-// (sn > 0: src is the window tensor [B][sn][sn][stride] of the plane's
-// pixels [sy0, sy0 + sn)^2, zero outside it)
+                      const uint16_t* mask, int mask_n, int mask_o, uint16_t* out_masked, int split, float* out2,
+                      hipStream_t st);
 int ls_bf16_mask_round_ex(const float* src, int stride, int coff, const uint16_t* act, const float* low, int B, int H,
                           int C, uint16_t* out, hipStream_t st, int sy0 = 0, int sn = 0);
 

@@ -55,7 +55,10 @@ def test_all_tilings_agree(prec):
             y, gw, gx = _run(g, x, wt, gy, prec)
             assert np.array_equal(y, y0), (p, c)
             assert np.array_equal(gx, gx0), (p, c)
-            if p == 2:  # chunked weight-gradient sums: same terms, other grouping
+            # chunked weight-gradient sums: same terms, other grouping (the
+            # input-gradient tiling of the head and dec1b also decides whether
+            # decoder level 1 runs on windows, which regroups its sums)
+            if p in (1, 2):
                 assert np.linalg.norm(gw - gw0) <= 1e-5 * np.linalg.norm(gw0), (p, c)
             else:
                 assert np.array_equal(gw, gw0), (p, c)

@@ -370,9 +370,11 @@ def test_bf16_backward_without_grad_x_all_active():
 
 @pytest.mark.parametrize("pad", [16, 4, 0])
 def test_bf16_backward_windows_equal_whole_planes(pad):
-    """The windowed level-1 gradients (no grad_x) against the whole-plane
-    path (grad_x requested): the same masked BF16 gradients, summed over
-    other pixel chunks, so per layer equal up to FP32 summation order."""
+    """Decoder level 1 on windows (the default: saved A9 / A10 and their
+    gradients as window tensors) against whole planes (forced by a direct
+    input-gradient tiling for the head): the same values per pixel, so the
+    input gradient equal and the weight gradient per layer equal up to the
+    grouping of its FP32 partial sums; with saved activations too."""
     res = 64
     region = synth.Region(tiles_x=2, tiles_y=2, res=res, pad=pad)
     g = ls.Grid.of(region)
@@ -383,13 +385,28 @@ def test_bf16_backward_windows_equal_whole_planes(pad):
     wt = torch.from_numpy(wts.astype(np.float32)).cuda()
     wb = ls.pack_weights_bf16(wt)
     gy = torch.randn((3, res, res, 4), device="cuda", generator=gen)
-    gw_w, _ = ls.refine_backward(wt, x, gy, g, ls.BF16, w_bf16=wb, want_grad_x=False)
-    gw_f, _ = ls.refine_backward(wt, x, gy, g, ls.BF16, w_bf16=wb, want_grad_x=True)
-    torch.cuda.synchronize()
-    layers = _layer_rel(gw_w.cpu().numpy().astype(np.float64), gw_f.cpu().numpy().astype(np.float64))
-    print(f"pad {pad}: windowed vs whole planes " + " ".join(f"{n} {r:.1e}" for n, r in layers))
-    for n, r in layers:
-        assert r <= 1e-5, (n, r)
+
+    def run():
+        act = torch.empty(ls.act_bytes(g, 3, ls.BF16), dtype=torch.uint8, device="cuda")
+        y, _ = ls.refine_tiles(wt, x, None, g, ls.BF16, w_bf16=wb, act_save=act, want_tex=False)
+        gw, gx = ls.refine_backward(wt, x, gy, g, ls.BF16, w_bf16=wb, act_save=act, want_grad_x=True)
+        gw2, _ = ls.refine_backward(wt, x, gy, g, ls.BF16, w_bf16=wb, want_grad_x=False)
+        torch.cuda.synchronize()
+        return [t.cpu().numpy().astype(np.float64) for t in (y, gw, gx, gw2)]
+
+    y_w, gw_w, gx_w, gw2_w = run()
+    ls.set_conv_config(10, ls.BF16, 1, 0)
+    try:
+        y_f, gw_f, gx_f, gw2_f = run()
+    finally:
+        ls.set_conv_config(10, ls.BF16, 1, -1)
+    assert np.array_equal(y_w, y_f)
+    assert np.array_equal(gx_w, gx_f)
+    for a, b in ((gw_w, gw_f), (gw2_w, gw_f), (gw2_f, gw_f)):
+        layers = _layer_rel(a, b)
+        print(f"pad {pad}: " + " ".join(f"{n} {r:.1e}" for n, r in layers))
+        for n, r in layers:
+            assert r <= 1e-5, (n, r)
 
 
 def test_backward_bf16_saved_activations_equal_recompute():
