@@ -237,10 +237,10 @@ int ls_lsnet_refine_tiles(const float* w, int precision, int32_t inputs, const f
  * output, writes grad_w [num_params] (overwritten, summed over the batch) and,
  * if non-null, grad_x [n_tiles][R][R][8].  act_save: the buffer filled by
  * ls_refine_tiles with the same inputs and precision, or NULL to recompute
- * the forward inside (activation recomputation).  LS_BF16 without grad_x:
- * the gradients of the decoder's full-resolution level are computed only
- * near the crop, where they can be nonzero (same values; the weight
- * gradient's FP32 partial sums are grouped differently).
+ * the forward inside (activation recomputation).  LS_BF16: the decoder's
+ * full-resolution level and its gradients are computed only near the crop,
+ * where the head reads them (same values; the weight gradient's FP32
+ * partial sums are grouped differently from a whole-plane computation).
  * Errors: LS_EINVAL for a null grad_w or (n_tiles > 0) null w, x or grad_y,
  * or a null w_bf16 with LS_BF16; LS_ERANGE for another precision;
  * LS_EWORKSPACE for a short workspace.
