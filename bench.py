@@ -81,6 +81,59 @@ def unet_flops(res: int, pad: int, inference: bool = True) -> float:
     return float(total)
 
 
+def train_flops(res: int, pad: int, grad_x: bool = False) -> float:
+    """FLOPs one tile's training step cannot avoid: the forward as inference
+    runs it (its output is the crop), then per layer the weight gradient
+    over the pixels where the layer's output gradient can be nonzero and the
+    input gradient over those where its input gradient can be (both grow by
+    one texel per 3x3 conv from the crop, halve or double through the
+    upsampling and the pools); the network input's gradient, and the head
+    input skip's 8 channels, only with grad_x."""
+    R = res + 2 * pad
+    R2, R4 = R // 2, R // 4
+
+    def grow(iv, n):
+        return max(0, iv[0] - 1), min(n, iv[1] + 1)
+
+    def half(iv, n):
+        return iv[0] // 2, min(n, -(-iv[1] // 2))
+
+    def dbl(iv, n):
+        return 2 * iv[0], min(n, 2 * iv[1])
+
+    def hull(a, b):
+        return min(a[0], b[0]), max(a[1], b[1])
+
+    def size(iv):
+        return (iv[1] - iv[0]) ** 2
+
+    crop = (pad, pad + res)
+    g10 = grow(crop, R)
+    g9 = grow(g10, R)
+    gu1 = grow(g9, R)
+    g8 = half(gu1, R2)
+    g7 = grow(g8, R2)
+    gu2 = grow(g7, R2)
+    g6 = half(gu2, R4)
+    g5 = grow(g6, R4)
+    gp2 = grow(g5, R4)
+    g4 = hull(gu2, dbl(gp2, R2))
+    g3 = grow(g4, R2)
+    gp1 = grow(g3, R2)
+    g2 = hull(gu1, dbl(gp1, R))
+    g1 = grow(g2, R)
+    g0 = grow(g1, R)
+    # per layer: (output-gradient window, input-gradient window or None)
+    wins = [(g1, g0 if grad_x else None), (g2, g1), (g3, gp1), (g4, g3), (g5, gp2), (g6, g5), (g7, gu2), (g8, g7),
+            (g9, gu1), (g10, g9), (crop, g10)]
+    total = unet_flops(res, pad, inference=True)
+    for l, ((_, ci, co), (wo, wi)) in enumerate(zip(synth.UNET_SHAPES, wins)):
+        total += 2 * size(wo) * co * 9 * ci
+        if wi is not None:
+            total += 2 * size(wi) * (16 if l == len(wins) - 1 and not grad_x else ci) * 9 * co
+    return float(total)
+
+
 def unet_bytes(res: int, pad: int) -> float:
     """HBM bytes one tile's BF16 forward must move at least, as the library
     runs it: every layer up to dec1a reads its inputs once and writes its
@@ -544,11 +597,17 @@ def bench_training(dev, train_steps: int = 60):
 
         ms = Timer().run(step, 5, 2)
         ms_rc = Timer().run(step_recompute, 5, 2)
-        flops = 3 * unet_flops(g.res, g.pad, inference=False) * nt  # forward + input gradient + weight gradient
+        # forward + input gradient + weight gradient, each on whole planes
+        flops = 3 * unet_flops(g.res, g.pad, inference=False) * nt
+        # what the step cannot avoid (windows around the crop, no grad_x)
+        flops_min = train_flops(g.res, g.pad) * nt
+        peak = PEAK_BF16_TFLOPS if prec == ls.BF16 else PEAK_FP32_TFLOPS
         out[name] = {"fwd_bwd_ms": ms, "tiles_per_s": nt / (ms * 1e-3), "fwd_bwd_recompute_ms": ms_rc,
                      "achieved_TFLOPs": flops / (ms * 1e-3) / 1e12,
-                     "frac_peak": flops / (ms * 1e-3) / 1e12 / (PEAK_BF16_TFLOPS if prec == ls.BF16
-                                                                else PEAK_FP32_TFLOPS),
+                     "frac_peak": flops / (ms * 1e-3) / 1e12 / peak,
+                     "flops_per_tile": {"whole_planes_3x_forward": flops / nt, "unavoidable": flops_min / nt},
+                     "achieved_TFLOPs_unavoidable": flops_min / (ms * 1e-3) / 1e12,
+                     "frac_peak_unavoidable": flops_min / (ms * 1e-3) / 1e12 / peak,
                      "saved_activation_bytes": int(act.numel()),
                      "autotune": {"ms_default": tune["ms_default"], "ms_tuned": tune["ms_tuned"],
                                   "choice": tune["choice"]}}
