@@ -48,7 +48,7 @@ constexpr int STAR_MAX_STEPS = 1024;     // safeguard on one point's star walk
 constexpr uint64_t FACE_NONE = ~0ull;
 constexpr int SUCC_K = 8;                // cached star successors per point
 constexpr uint64_t SUCC_EMPTY = ~0ull;
-constexpr int SEARCH_MAX_HITS = 12;      // a wave searches once at most this many lanes can step from the lists
+constexpr int SEARCH_MAX_HITS = 8;       // a wave searches once at most this many lanes can step from the lists
 constexpr int SORT_LDS = 16384;          // bin segments up to this size sort in LDS
 
 struct BinParams {
