@@ -1314,6 +1314,9 @@ struct Conv2Args {
   uint16_t* out_bf16;  // l2 output [B][Ho][Wo][cout2], or null
   float* out_f32;      // same layout, or null
   uint16_t* pool_out;  // 2 x 2 average pool of the BF16 output [B][Ho/2][Wo/2][cout2], or null
+  // out_bf16 is stored only on [st0, st1)^2 of the output window (the rest
+  // is never read; the pool still sees every pixel)
+  int st0 = 0, st1 = 1 << 30;
 };
 
 // Products of one 16 x 16 output tile from a staged 18 x 18 patch (pitch
@@ -1539,7 +1542,7 @@ __global__ void __launch_bounds__(256, MINW) k_conv2_bf16(Conv2Args A) {
       for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) h[mt][r] = f2bf(q[mt][r]);
-        if (A.out_bf16 && ok(mt)) {
+        if (A.out_bf16 && ok(mt) && oyr + mt >= A.st0 && oyr + mt < A.st1 && oxr >= A.st0 && oxr < A.st1) {
           uint2 u;
           u.x = (uint32_t)h[mt][0] | ((uint32_t)h[mt][1] << 16);
           u.y = (uint32_t)h[mt][2] | ((uint32_t)h[mt][3] << 16);
@@ -1579,7 +1582,7 @@ __global__ void __launch_bounds__(256, MINW) k_conv2_bf16(Conv2Args A) {
 // compiled form; LS_ENOTIMPL otherwise.
 int conv2_bf16(const SrcPart& a1, const SrcPart& b2, int B, int H, int l1, int l2, const uint16_t* packed,
                const float* w, uint16_t* out_bf16, float* out_f32, uint16_t* pool_out, int relu2, int y0, int x0,
-               int Ho, int Wo, hipStream_t st) {
+               int Ho, int Wo, hipStream_t st, int st0 = 0, int st1 = 1 << 30) {
   if (LS_LAYERS[l1].cout != 16 || LS_LAYERS[l2].cin != 16 + b2.c || a1.c != LS_LAYERS[l1].cin) return LS_ENOTIMPL;
   if (a1.up || b2.up || (pool_out && (Ho % 2 || Wo % 2))) return LS_ENOTIMPL;
   Conv2Args a;
@@ -1603,6 +1606,8 @@ int conv2_bf16(const SrcPart& a1, const SrcPart& b2, int B, int H, int l1, int l
   a.out_bf16 = out_bf16;
   a.out_f32 = out_f32;
   a.pool_out = pool_out;
+  a.st0 = st0;
+  a.st1 = st1;
   const int64_t nblk = (int64_t)B * a.tiles_x * a.tiles_y;
   if (nblk <= 0) return LS_OK;
   if (nblk >= ((int64_t)1 << 31)) return LS_ENOTIMPL;
@@ -1694,7 +1699,15 @@ int ls_bf16_forward(const float* w, const uint16_t* packed, const float* x, int 
   SrcPart u8 = bpart(A8, 32, R2);
   u8.up = 1;
   int rc01 = LS_ENOTIMPL;
-  if (fused(1)) rc01 = conv2_bf16(X, none, B, R, 0, 1, packed, w, A2, nullptr, P1, 1, 0, 0, R, R, st);
+  // with the head pair fused (inference), A2 is read only by dec1a on its
+  // window grown by one texel: the fused enc1a + enc1b stores just that part
+  int a2_0 = 0, a2_1 = 1 << 30;
+  const int64_t head_tiles = (int64_t)B * ((gi.res + FT - 1) / FT) * ((gi.res + FT - 1) / FT);
+  if (fused(10) && head_tiles < ((int64_t)1 << 31)) {  // the fused head pair then runs (no whole-plane dec1a)
+    a2_0 = std::max(0, gi.pad - 3);
+    a2_1 = std::min(R, gi.pad + gi.res + 3);
+  }
+  if (fused(1)) rc01 = conv2_bf16(X, none, B, R, 0, 1, packed, w, A2, nullptr, P1, 1, 0, 0, R, R, st, a2_0, a2_1);
   if (rc01 == LS_ENOTIMPL) {
     LS_TRYB(conv(cs(X, none), R, 0, A1, nullptr));
     LS_TRYB(conv(cs(bpart(A1, 16, R), none), R, 1, A2, P1));
