@@ -84,3 +84,17 @@ def test_train_flops_below_whole_planes():
     R = 64
     skip = 2 * R * R * 16 * 9 * 8 + 2 * R * R * 8 * 9 * 4
     assert bench.train_flops(64, 0, grad_x=False) == pytest.approx(3 * bench.unet_flops(64, 0, inference=False) - skip)
+
+
+def test_binning_memberships_match_the_oracle_binning():
+    """The binning figure's window-membership count (8 B read per point, 4 B
+    written per membership) equals what the oracle's binning produces."""
+    import oracle
+
+    w = synth.batch_tiles(seed=2, tiles_x=6, tiles_y=5)
+    x, y, _, _ = w.points.numpy()
+    tiles = np.arange(w.region.tiles_x * w.region.tiles_y, dtype=np.int32)
+    _, idx = oracle.bin_points(w.region, x, y, tiles)
+    r = bench.binning_rate(w.region, w.points.x, w.points.y, {"bin_count": 0.01, "bin_scan": 0.01, "bin_scatter": 0.01})
+    assert r["memberships"] == len(idx)
+    assert r["points"] == len(x)
