@@ -137,13 +137,19 @@ __global__ void __launch_bounds__(PT_THREADS) k_splat_mean(MeanParams p) {
     if (u.n) flush(cur, u);
     if (window) {
       __syncthreads();
+      // one lane per (texel, field): the lanes of one atomic instruction
+      // cover whole 40-byte texel records rather than one field of 64
+      // texels spread over eight rows
       const int span = (int)(hi - lo) + 1;
-      for (int w = tid; w < span; w += PT_THREADS) {
-        const uint32_t cnt = s_c[w][3];
-        if (!cnt) continue;
+      for (int i = tid; i < 5 * span; i += PT_THREADS) {
+        const int w = i / 5, f = i - 5 * w;
+        if (!s_c[w][3]) continue;
         const uint32_t code = lo + (uint32_t)w;
-        add_global(p.acc + 5 * texel_index(G, (int)compact16(code), (int)compact16(code >> 1)),
-                   (long long)s_z[w], s_c[w][0], s_c[w][1], s_c[w][2], cnt);
+        const unsigned long long v = f == 0 ? s_z[w] : (unsigned long long)s_c[w][f - 1];
+        atomicAdd(p.acc + 5 * texel_index(G, (int)compact16(code), (int)compact16(code >> 1)) + f, v);
+      }
+      __syncthreads();
+      for (int w = tid; w < span; w += PT_THREADS) {
         s_z[w] = 0;
         s_c[w][0] = s_c[w][1] = s_c[w][2] = s_c[w][3] = 0;
       }
