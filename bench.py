@@ -842,7 +842,9 @@ def bench_point_kernels(dev, n_points: int = 100_000_000):
     out = {"splat_mean": {"workload": f"{n_points} points, 64 x 64 tiles, Morton-ordered", "ms": ms,
                           "points_per_s": n_points / (ms * 1e-3), "algorithmic_GBps": alg / (ms * 1e-3) / 1e9,
                           "frac_hbm_peak": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                          "algorithmic_bytes": "18 B per point + 40 B of sums per texel"}}
+                          "algorithmic_bytes": "18 B per point + 40 B of sums per texel",
+                          "traffic": recorded_traffic("ls_target.hip", "splat_mean_100M_points_traffic.md"),
+                          "traffic_unit": "HBM bytes per launch (counters)"}}
     del acc
     # a perspective view over the region from 3 km up, 1920 x 1080
     side = 64 * 640.0
